@@ -1,0 +1,196 @@
+/*
+ * canny.h -- C ABI of the MI355X (gfx950) Canny edge detector library
+ * (libcanny.so).
+ *
+ * The operator is the paper's four-step pipeline (Section 2.2.1, Steps 1-4;
+ * step order of Algorithm 1): noise filter, Sobel gradient strength and
+ * direction, non-maximum suppression, and hysteresis with a lower and an
+ * upper threshold.  The readings of what the paper leaves open are fixed
+ * here and stated per call: replicate (clamp-to-edge) borders at every
+ * stage, ties in non-maximum suppression go to the earlier pixel in raster
+ * order, strong = strength > high, weak = low <= strength <= high,
+ * 8-connected hysteresis through weak pixels.
+ *
+ * Conventions for every call:
+ *  - Pointers are DEVICE pointers owned by the caller unless marked "host".
+ *    The library never frees, reallocates or retains them past the call.
+ *  - Images are row-major with a row pitch given in ELEMENTS (bytes for
+ *    uint8 images, floats for float images); pitch >= W.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Every call only
+ *    enqueues work on `stream` and returns; results are valid once the
+ *    stream has been synchronised.  No call synchronises the host.
+ *  - Arguments are validated before anything is enqueued.  On an invalid
+ *    argument the call returns CANNY_ERR_INVALID (too-small workspace:
+ *    CANNY_ERR_WORKSPACE) and writes nothing.  A launch failure reported by
+ *    the HIP runtime returns CANNY_ERR_HIP.  No C++ exception crosses the ABI.
+ *  - Calls on different streams with distinct workspaces may overlap.
+ *  - Class map ("class2"): 2 bits per pixel, 4 pixels per byte, pixel x of a
+ *    row at bits 2*(x%4)..2*(x%4)+1 of byte x/4 (LSB first); codes 0 = none,
+ *    1 = weak, 2 = strong.  Row pitch is canny_class_pitch(W) bytes.  Bits of
+ *    pixels x >= W in the last byte of a row are 0; padding bytes past
+ *    ceil(W/4) are unspecified.
+ *  - Edge maps are uint8: 255 on an edge pixel, 0 elsewhere.
+ */
+#ifndef CANNY_H
+#define CANNY_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    CANNY_OK = 0,
+    CANNY_ERR_INVALID = 1,     /* bad argument; nothing enqueued        */
+    CANNY_ERR_WORKSPACE = 2,   /* workspace missing or too small        */
+    CANNY_ERR_HIP = 3,         /* the HIP runtime reported an error      */
+    CANNY_ERR_UNSUPPORTED = 4  /* device is not gfx950                  */
+};
+
+/* Human-readable name of a status code (static string, never NULL). */
+const char* canny_status_string(int status);
+
+/* Library ABI version (incremented on any signature change). */
+int canny_abi_version(void);
+
+/* Row pitch in bytes of the 2-bit class map for width W:
+ * ceil(W/4) rounded up to a multiple of 4.  Returns 0 if W < 1. */
+int64_t canny_class_pitch(int W);
+
+/* ---------------------------------------------------------------------
+ * Integer Canny (Steps 1-4 on uint8 images).
+ *
+ * Step 1: 5x5 binomial filter, weights (1,4,6,4,1) per axis, one rounding
+ *         of the exact sum: B = (S + 128) >> 8.
+ * Step 2: Sobel pair (correlation, x right, y down) in int32,
+ *         strength M = |Gx| + |Gy| (0..2040), direction = the nearest of
+ *         0/45/90/135 degrees to atan2(Gy, Gx) (computed exactly in integers).
+ * Step 3: keep p iff M(p) > M(p - d) and M(p) >= M(p + d), d the direction.
+ * Step 4: class 2 if kept and M > high, class 1 if kept and M >= low;
+ *         edge iff class >= 1 and 8-connected through class >= 1 pixels to a
+ *         class-2 pixel.
+ *
+ * in          uint8 H x W, pitch in_pitch bytes.
+ * low, high   0 <= low <= high (values above 2040 never match).
+ * edges       uint8 H x W output, pitch edges_pitch bytes; may be NULL if
+ *             only the class map is wanted (then Step 4's connectivity pass
+ *             is skipped).
+ * class2      optional class-map output (see conventions) or NULL.
+ * ws          device workspace of at least canny_u8_workspace_bytes(H, W)
+ *             bytes, 256-byte aligned; contents on entry are ignored.
+ * Errors: NULL in, H or W < 1, pitch < W, low < 0, low > high, in aliasing
+ *         an output -> CANNY_ERR_INVALID.
+ */
+size_t canny_u8_workspace_bytes(int H, int W);
+int canny_u8(const uint8_t* in, int64_t in_pitch, int H, int W, int32_t low, int32_t high,
+             uint8_t* edges, int64_t edges_pitch, uint8_t* class2, void* ws, size_t ws_bytes,
+             void* stream);
+
+/* ---------------------------------------------------------------------
+ * Hysteresis alone (Step 4 connectivity) on a caller-provided class map.
+ *
+ * class2      packed class map (see conventions), pitch canny_class_pitch(W),
+ *             4-byte aligned; bits of pixels x >= W are ignored.
+ * edges       uint8 H x W output (255 / 0), pitch edges_pitch bytes.
+ * ws          at least canny_hysteresis_workspace_bytes(H, W) bytes.
+ * An edge pixel is a class >= 1 pixel 8-connected through class >= 1 pixels
+ * to a class-2 pixel.  Computed by union-find connected-component labelling;
+ * the result does not depend on the order of work.
+ */
+size_t canny_hysteresis_workspace_bytes(int H, int W);
+int canny_hysteresis(const uint8_t* class2, int H, int W, uint8_t* edges, int64_t edges_pitch,
+                     void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------
+ * Float Canny (Steps 1-4 on fp32 images, fp32 arithmetic).
+ *
+ * Step 1: Gaussian filter, taps k = -radius..radius sampled from
+ *         exp(-k^2 / (2 sigma^2)) and normalised to sum 1 (separable).
+ * Step 2: Sobel pair, strength M = sqrt(Gx^2 + Gy^2).
+ * Step 3: continuous-direction suppression: M is compared with the two
+ *         values interpolated linearly on the ring of the 3x3 neighbourhood
+ *         where the gradient line leaves it; keep iff M > back and
+ *         M >= forward (forward = the side whose dominant-axis step is
+ *         positive); M = 0 is never kept.
+ * Step 4: thresholds low/high (if relative != 0, multiplied on the device
+ *         by the image's largest M before suppression), classes and
+ *         hysteresis as in the integer path.
+ *
+ * in          float H x W, pitch in_pitch floats.
+ * sigma > 0, 1 <= radius <= 16, 0 <= low <= high.
+ * edges       uint8 output or NULL (class map only).
+ * class2      optional class-map output or NULL.
+ * mag_out     optional float H x W strength output (pitch W) or NULL.
+ * max_out     optional device float receiving the largest M, or NULL.
+ * ws          at least canny_f32_workspace_bytes(H, W) bytes.
+ */
+size_t canny_f32_workspace_bytes(int H, int W);
+int canny_f32(const float* in, int64_t in_pitch, int H, int W, float sigma, int radius,
+              float low, float high, int relative, uint8_t* edges, int64_t edges_pitch,
+              uint8_t* class2, float* mag_out, float* max_out, void* ws, size_t ws_bytes,
+              void* stream);
+
+/* ---------------------------------------------------------------------
+ * Batched integer Canny over many images of uneven sizes.
+ *
+ * The same operator as canny_u8, applied to n independent images.  The
+ * plan fixes the image sizes and thresholds, picks tile shapes (from an
+ * on-disk autotune cache, by timing candidates when autotune != 0, else a
+ * default), and records one HIP graph whose kernels each cover every tile
+ * of every image in a single persistent launch (a device-side tile counter
+ * hands out work).  canny_batch writes the per-image pointer table to the
+ * device and replays the graph on `stream`.
+ *
+ * canny_batch_plan_create: n >= 1; H, W host arrays of n sizes (>= 1 each);
+ *   0 <= low <= high; *out receives a host-owned plan.  May allocate device
+ *   memory (owned by the plan) and, with autotune != 0, run timing launches
+ *   on the current device; it synchronises the device.
+ * canny_batch_workspace_bytes: workspace canny_batch needs.
+ * canny_batch: in / edges are HOST arrays of n device pointers, in_pitch /
+ *   edges_pitch HOST arrays of n pitches (bytes).  Returns
+ *   CANNY_ERR_INVALID on NULL or pitch < W.  Calls with the same plan must
+ *   not overlap (the plan's pointer table and graph are shared).
+ * canny_batch_plan_info: host copies of the chosen forward rows-per-wave,
+ *   hysteresis tile height and persistent workgroups per CU.
+ */
+typedef struct canny_batch_plan canny_batch_plan;
+int canny_batch_plan_create(int n, const int32_t* H, const int32_t* W, int32_t low, int32_t high,
+                            int autotune, canny_batch_plan** out);
+size_t canny_batch_workspace_bytes(const canny_batch_plan* plan);
+int canny_batch(canny_batch_plan* plan, const uint8_t* const* in, const int64_t* in_pitch,
+                uint8_t* const* edges, const int64_t* edges_pitch, void* ws, size_t ws_bytes,
+                void* stream);
+int canny_batch_plan_info(const canny_batch_plan* plan, int32_t* fwd_rows, int32_t* hyst_rows,
+                          int32_t* wgs_per_cu);
+void canny_batch_plan_destroy(canny_batch_plan* plan);
+
+/* ---------------------------------------------------------------------
+ * Differentiable front end M(I, sigma) = |Sobel * G_sigma * I| (Steps 1-2,
+ * L2 strength), batched over N images of equal size, one sigma per image.
+ *
+ * canny_mag_forward: I float [N][H][W] contiguous, sigma float [N] (device),
+ *   radius 1..16 fixed for all images (the taps are renormalised per
+ *   sigma), M float [N][H][W] output.
+ * canny_mag_backward: given dM = dL/dM [N][H][W], writes dL/dI
+ *   [N][H][W] and dL/dsigma [N].  Replicate borders make each transposed
+ *   stencil fold onto the edge pixels; dM/dG is taken as 0 where M = 0.  The
+ *   blurred image is recomputed, not stored.  dsigma is reduced in a fixed
+ *   order (run-to-run identical).  ws: canny_mag_backward_workspace_bytes.
+ * Errors: NULL pointers, N, H, W < 1, radius outside 1..16 ->
+ *   CANNY_ERR_INVALID.  sigma values are read on the device; a sigma <= 0
+ *   gives unspecified output (no fault).
+ */
+int canny_mag_forward(const float* I, const float* sigma, int N, int H, int W, int radius,
+                      float* M, void* stream);
+size_t canny_mag_backward_workspace_bytes(int N, int H, int W, int radius);
+int canny_mag_backward(const float* I, const float* sigma, const float* dM, int N, int H, int W,
+                       int radius, float* dI, float* dsigma, void* ws, size_t ws_bytes,
+                       void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CANNY_H */

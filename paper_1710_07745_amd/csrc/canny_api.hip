@@ -1,0 +1,203 @@
+// C ABI of libcanny: argument validation, workspace layout and dispatch for
+// the single-image integer and float paths.  Every check runs before any
+// work is enqueued; no call synchronises the host.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <mutex>
+
+#include "../../include/canny.h"
+#include "canny_internal.h"
+
+namespace canny {
+
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+bool device_ok() {
+    static std::mutex mu;
+    static int cached[64];  // 0 unknown, 1 ok, 2 unsupported
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return false;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!cached[dev]) {
+        hipDeviceProp_t p;
+        if (hipGetDeviceProperties(&p, dev) != hipSuccess) return false;
+        cached[dev] = std::strncmp(p.gcnArchName, "gfx950", 6) == 0 ? 1 : 2;
+    }
+    return cached[dev] == 1;
+}
+
+bool size_ok(int H, int W) {
+    return H >= 1 && W >= 1 && H <= (1 << 20) && W <= (1 << 20) &&
+           (int64_t)H * W <= ((int64_t)1 << 34);
+}
+
+static bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+    if (!a || !b || !na || !nb) return false;
+    const char* pa = static_cast<const char*>(a);
+    const char* pb = static_cast<const char*>(b);
+    return pa < pb + nb && pb < pa + na;
+}
+
+static size_t image_bytes(int H, int64_t pitch, int W, size_t elem) {
+    return ((size_t)(H - 1) * (size_t)pitch + (size_t)W) * elem;
+}
+
+int64_t class_pitch(int W) { return W < 1 ? 0 : ((int64_t)ceil_div(W, 4) + 3) & ~(int64_t)3; }
+
+static size_t class_bytes(int H, int W) { return align256((size_t)H * class_pitch(W)); }
+
+static int status_of(hipError_t e) { return e == hipSuccess ? CANNY_OK : CANNY_ERR_HIP; }
+
+}  // namespace canny
+
+using namespace canny;
+
+extern "C" {
+
+const char* canny_status_string(int status) {
+    switch (status) {
+        case CANNY_OK: return "ok";
+        case CANNY_ERR_INVALID: return "invalid argument";
+        case CANNY_ERR_WORKSPACE: return "workspace missing or too small";
+        case CANNY_ERR_HIP: return "HIP runtime error";
+        case CANNY_ERR_UNSUPPORTED: return "unsupported device (gfx950 required)";
+        default: return "unknown status";
+    }
+}
+
+int canny_abi_version(void) { return 1; }
+
+int64_t canny_class_pitch(int W) { return class_pitch(W); }
+
+size_t canny_u8_workspace_bytes(int H, int W) {
+    if (!size_ok(H, W)) return 0;
+    return class_bytes(H, W) + hyst_workspace_bytes(H, W, hyst_tile_rows_default());
+}
+
+int canny_u8(const uint8_t* in, int64_t in_pitch, int H, int W, int32_t low, int32_t high,
+             uint8_t* edges, int64_t edges_pitch, uint8_t* class2, void* ws, size_t ws_bytes,
+             void* stream) {
+    if (!in || !size_ok(H, W) || in_pitch < W || low < 0 || low > high) return CANNY_ERR_INVALID;
+    if (edges && edges_pitch < W) return CANNY_ERR_INVALID;
+    if (class2 && ((uintptr_t)class2 % 4)) return CANNY_ERR_INVALID;
+    const size_t nin = image_bytes(H, in_pitch, W, 1);
+    if (edges && overlaps(in, nin, edges, image_bytes(H, edges_pitch, W, 1))) return CANNY_ERR_INVALID;
+    if (class2 && overlaps(in, nin, class2, (size_t)H * class_pitch(W))) return CANNY_ERR_INVALID;
+    const size_t need = canny_u8_workspace_bytes(H, W);
+    if (!ws || ws_bytes < need || ((uintptr_t)ws % 256)) return CANNY_ERR_WORKSPACE;
+    if (!device_ok()) return CANNY_ERR_UNSUPPORTED;
+
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* w = static_cast<char*>(ws);
+    U8FwdArgs f;
+    f.in = in;
+    f.pitch = in_pitch;
+    f.H = H;
+    f.W = W;
+    f.low = low > 2041 ? 2041 : low;
+    f.high = high > 2040 ? 2040 : high;
+    f.cls = class2 ? class2 : reinterpret_cast<uint8_t*>(w);
+    f.cpitch = class_pitch(W);
+    hipError_t e = launch_u8_forward(f, 32, s);
+    if (e != hipSuccess || !edges) return status_of(e);
+    HystArgs h;
+    h.cls = f.cls;
+    h.cpitch = f.cpitch;
+    h.H = H;
+    h.W = W;
+    h.edges = edges;
+    h.epitch = edges_pitch;
+    const int T = hyst_tile_rows_default();
+    hyst_carve(w + class_bytes(H, W), H, W, T, h);
+    return status_of(launch_hysteresis(h, T, s));
+}
+
+size_t canny_hysteresis_workspace_bytes(int H, int W) {
+    if (!size_ok(H, W)) return 0;
+    return hyst_workspace_bytes(H, W, hyst_tile_rows_default());
+}
+
+int canny_hysteresis(const uint8_t* class2, int H, int W, uint8_t* edges, int64_t edges_pitch,
+                     void* ws, size_t ws_bytes, void* stream) {
+    if (!class2 || !edges || !size_ok(H, W) || edges_pitch < W || ((uintptr_t)class2 % 4))
+        return CANNY_ERR_INVALID;
+    if (overlaps(class2, (size_t)H * class_pitch(W), edges, image_bytes(H, edges_pitch, W, 1)))
+        return CANNY_ERR_INVALID;
+    const size_t need = canny_hysteresis_workspace_bytes(H, W);
+    if (!ws || ws_bytes < need || ((uintptr_t)ws % 256)) return CANNY_ERR_WORKSPACE;
+    if (!device_ok()) return CANNY_ERR_UNSUPPORTED;
+    HystArgs h;
+    h.cls = class2;
+    h.cpitch = class_pitch(W);
+    h.H = H;
+    h.W = W;
+    h.edges = edges;
+    h.epitch = edges_pitch;
+    const int T = hyst_tile_rows_default();
+    hyst_carve(ws, H, W, T, h);
+    return status_of(launch_hysteresis(h, T, static_cast<hipStream_t>(stream)));
+}
+
+size_t canny_f32_workspace_bytes(int H, int W) {
+    if (!size_ok(H, W)) return 0;
+    return 256 + class_bytes(H, W) + hyst_workspace_bytes(H, W, hyst_tile_rows_default());
+}
+
+int canny_f32(const float* in, int64_t in_pitch, int H, int W, float sigma, int radius, float low,
+              float high, int relative, uint8_t* edges, int64_t edges_pitch, uint8_t* class2,
+              float* mag_out, float* max_out, void* ws, size_t ws_bytes, void* stream) {
+    if (!in || !size_ok(H, W) || in_pitch < W) return CANNY_ERR_INVALID;
+    if (!(sigma > 0.0f) || !std::isfinite(sigma) || radius < 1 || radius > 8) return CANNY_ERR_INVALID;
+    if (!(low >= 0.0f) || !(high >= low) || !std::isfinite(high)) return CANNY_ERR_INVALID;
+    if (edges && edges_pitch < W) return CANNY_ERR_INVALID;
+    if (class2 && ((uintptr_t)class2 % 4)) return CANNY_ERR_INVALID;
+    const size_t nin = image_bytes(H, in_pitch, W, 4);
+    if (edges && overlaps(in, nin, edges, image_bytes(H, edges_pitch, W, 1))) return CANNY_ERR_INVALID;
+    if (class2 && overlaps(in, nin, class2, (size_t)H * class_pitch(W))) return CANNY_ERR_INVALID;
+    if (mag_out && overlaps(in, nin, mag_out, (size_t)H * W * 4)) return CANNY_ERR_INVALID;
+    const size_t need = canny_f32_workspace_bytes(H, W);
+    if (!ws || ws_bytes < need || ((uintptr_t)ws % 256)) return CANNY_ERR_WORKSPACE;
+    if (!device_ok()) return CANNY_ERR_UNSUPPORTED;
+
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* w = static_cast<char*>(ws);
+    F32FwdArgs f;
+    std::memset(&f, 0, sizeof(f));
+    f.in = in;
+    f.pitch = in_pitch;
+    f.H = H;
+    f.W = W;
+    {  // sampled Gaussian taps, normalised in double, rounded once to float
+        double gd[17], sum = 0.0;
+        for (int k = 0; k <= radius; ++k) {
+            gd[k] = std::exp(-(double)k * k / (2.0 * (double)sigma * (double)sigma));
+            sum += k ? 2.0 * gd[k] : gd[k];
+        }
+        for (int k = 0; k <= radius; ++k) f.g[k] = (float)(gd[k] / sum);
+    }
+    f.radius = radius;
+    f.low = low;
+    f.high = high;
+    f.relative = relative ? 1 : 0;
+    f.maxbits = reinterpret_cast<uint32_t*>(w);
+    f.cls = class2 ? class2 : reinterpret_cast<uint8_t*>(w + 256);
+    f.cpitch = class_pitch(W);
+    f.mag = mag_out;
+    f.max_out = max_out;
+    hipError_t e = launch_f32_forward(f, s);
+    if (e != hipSuccess || !edges) return status_of(e);
+    HystArgs h;
+    h.cls = f.cls;
+    h.cpitch = f.cpitch;
+    h.H = H;
+    h.W = W;
+    h.edges = edges;
+    h.epitch = edges_pitch;
+    const int T = hyst_tile_rows_default();
+    hyst_carve(w + 256 + class_bytes(H, W), H, W, T, h);
+    return status_of(launch_hysteresis(h, T, s));
+}
+
+}  // extern "C"

@@ -1,0 +1,111 @@
+// Internal declarations shared by the HIP translation units of libcanny.
+// Device helpers (packed 16-bit arithmetic, cross-lane moves) and the host
+// launchers each kernel file exports to the ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace canny {
+
+// ---------------------------------------------------------------- constants
+constexpr int kWave = 64;
+constexpr int kWavesPerWG = 4;
+constexpr int kWGThreads = kWave * kWavesPerWG;
+
+// Integer forward: one wave covers 64 lanes x 4 pixels; lanes 0 and 63 carry
+// the 4-pixel halo (2 blur + 1 Sobel + 1 suppression), so 62 lanes produce.
+constexpr int kU8StripCols = 62 * 4;  // 248 output columns per wave
+
+// Hysteresis tile: 64 columns (16 class-map bytes) x kHystRows rows.
+constexpr int kHystCols = 64;
+
+// ---------------------------------------------------------------- helpers
+template <typename To, typename From>
+__device__ __forceinline__ To bc(From v) { return __builtin_bit_cast(To, v); }
+
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+typedef short i16x2 __attribute__((ext_vector_type(2)));
+
+__host__ __device__ constexpr inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
+__host__ __device__ constexpr inline int64_t ceil_div64(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// lane i receives lane i-1's value (lane 0 receives 0)
+__device__ __forceinline__ uint32_t from_left(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x138, 0xF, 0xF, true);
+}
+// lane i receives lane i+1's value (lane 63 receives 0)
+__device__ __forceinline__ uint32_t from_right(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x130, 0xF, 0xF, true);
+}
+__device__ __forceinline__ float from_left_f(float v) { return bc<float>(from_left(bc<uint32_t>(v))); }
+__device__ __forceinline__ float from_right_f(float v) { return bc<float>(from_right(bc<uint32_t>(v))); }
+
+// A pointer the caller knows to be wave-uniform, moved to scalar registers so
+// that per-lane accesses use the scalar-base + 32-bit-offset address form.
+template <typename T>
+__device__ __forceinline__ T* uniform_ptr(T* p) {
+    const uint64_t v = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return reinterpret_cast<T*>(((uint64_t)hi << 32) | lo);
+}
+
+// Workgroup index remapped so that each XCD (8 per chip, fed round-robin)
+// walks a contiguous range of logical workgroups.
+__device__ __forceinline__ int xcd_remap(int wg, int nwg) {
+    const int per = (nwg + 7) >> 3;
+    const int xcd = wg & 7;
+    const int idx = wg >> 3;
+    // the first (nwg % 8) XCDs get `per` groups, the rest `per - 1`
+    const int rem = nwg & 7;
+    const int full = rem == 0 ? 8 : rem;
+    const int base = xcd < full ? xcd * per : full * per + (xcd - full) * (per - 1);
+    return base + idx;
+}
+
+// --------------------------------------------------------------- launchers
+struct U8FwdArgs {
+    const uint8_t* in;
+    int64_t pitch;
+    int H, W;
+    int low, high;  // clamped to the 16-bit range by the caller
+    uint8_t* cls;
+    int64_t cpitch;
+};
+hipError_t launch_u8_forward(const U8FwdArgs& a, int rows_per_wave, hipStream_t s);
+int u8_forward_supported_rows(int rows);
+
+struct HystArgs {
+    const uint8_t* cls;
+    int64_t cpitch;
+    int H, W;
+    uint8_t* edges;
+    int64_t epitch;
+    int32_t* blab;    // [ntiles * perim] border labels
+    int32_t* parent;  // [ntiles * perim] union-find forest over border labels
+    int32_t* flag;    // [ntiles * perim] strong flags
+};
+int hyst_tile_rows_default();
+size_t hyst_workspace_bytes(int H, int W, int tile_rows);
+void hyst_carve(void* ws, int H, int W, int tile_rows, HystArgs& a);
+hipError_t launch_hysteresis(const HystArgs& a, int tile_rows, hipStream_t s);
+
+struct F32FwdArgs {
+    const float* in;
+    int64_t pitch;
+    int H, W;
+    float g[17];  // taps 0..radius (symmetric)
+    int radius;
+    float low, high;
+    int relative;
+    uint32_t* maxbits;  // device scalar: float bits of max M (>= 0)
+    uint8_t* cls;
+    int64_t cpitch;
+    float* mag;       // optional
+    float* max_out;   // optional
+};
+hipError_t launch_f32_forward(const F32FwdArgs& a, hipStream_t s);
+
+}  // namespace canny

@@ -1,0 +1,355 @@
+// Fused integer Canny forward for gfx950: Steps 1-3 and the double threshold
+// of Step 4 (paper Section 2.2.1) in one pass over the uint8 image.
+//
+// Layout of the work: a wave owns a vertical strip.  Lane l holds the four
+// input columns c0 = X0 - 4 + 4l .. c0 + 3 as one dword; lanes 0 and 63 carry
+// the 4-column halo (2 for the blur, 1 for Sobel, 1 for suppression), so
+// lanes 1..62 produce 248 output columns.  The wave walks the strip top to
+// bottom; every stage keeps a sliding window of rows in registers:
+//     input row -> horizontal binomial (h, 5-row window)
+//               -> vertical binomial + rounding (B) -> Sobel row terms
+//                  (dx = B(x+1) - B(x-1), sx = B(x-1) + 2B(x) + B(x+1), 3 rows)
+//               -> Gx, Gy, M = |Gx| + |Gy|, direction masks (3 rows of M)
+//               -> suppression + thresholds -> 2-bit codes, 1 byte per lane.
+// Horizontal neighbours cross lanes with DPP wave shifts; all arithmetic is
+// packed 16-bit (two pixels per VGPR).  Values stay in range: horizontal
+// blur <= 4080, vertical blur + 128 <= 65408, |Gx|,|Gy| <= 1020, M <= 2040.
+//
+// Replicate borders are applied per stage: the input loads are clamped, and
+// the blurred image B and the strength M are re-extended after they are
+// formed (columns outside the image copy the edge column; rows outside copy
+// the edge row), so each stage reads its predecessor exactly as the
+// clamp-indexed definition does.
+//
+// Direction: the nearest multiple of 45 degrees to atan2(Gy, Gx).  For
+// |Gx|, |Gy| <= 1020 the tan(22.5 deg) boundary test is exact as
+// 408*|Gy| < 169*|Gx| (169/408 and 408/985 are consecutive continued-fraction
+// convergents of sqrt(2)-1; no fraction with denominator <= 1020 lies
+// between them), and the 67.5 deg test is the same with the axes swapped.
+// Both are single v_dot2 instructions on a packed (|Gy|, |Gx|) pair.
+#include "canny_internal.h"
+
+namespace canny {
+namespace {
+
+__device__ __forceinline__ u16x2 U(uint32_t v) { return bc<u16x2>(v); }
+__device__ __forceinline__ i16x2 S(uint32_t v) { return bc<i16x2>(v); }
+__device__ __forceinline__ uint32_t W32(u16x2 v) { return bc<uint32_t>(v); }
+__device__ __forceinline__ uint32_t W32(i16x2 v) { return bc<uint32_t>(v); }
+__device__ __forceinline__ uint32_t perm(uint32_t hi, uint32_t lo, uint32_t sel) {
+    return __builtin_amdgcn_perm(hi, lo, sel);
+}
+__device__ __forceinline__ uint32_t align16(uint32_t hi, uint32_t lo) {
+    return __builtin_amdgcn_alignbit(hi, lo, 16);
+}
+// per-bit select: m ? a : b
+__device__ __forceinline__ uint32_t bsel(uint32_t m, uint32_t a, uint32_t b) {
+    return (a & m) | (b & ~m);
+}
+
+// Border description of one wave strip (all fields wave-uniform except masks).
+struct Border {
+    bool left, right;       // strip touches column 0 / column W-1
+    int l0_lane;            // lane holding column 0
+    int lw_lane, lw_pair;   // lane and pair holding column W-1
+    int lw_shift;           // 0 or 16
+    uint32_t mL0, mL1;      // 16-bit halves whose column < 0
+    uint32_t mR0, mR1;      // 16-bit halves whose column >= W
+};
+
+// Replicate the edge column into halves outside the image.
+__device__ __forceinline__ void fix_cols(uint32_t& p0, uint32_t& p1, const Border& bd) {
+    if (bd.left) {
+        uint32_t v = (uint32_t)__builtin_amdgcn_readlane((int)p0, bd.l0_lane);
+        v = (v & 0xFFFFu) * 0x10001u;
+        p0 = bsel(bd.mL0, v, p0);
+        p1 = bsel(bd.mL1, v, p1);
+    }
+    if (bd.right) {
+        uint32_t src = bd.lw_pair ? p1 : p0;
+        uint32_t v = (uint32_t)__builtin_amdgcn_readlane((int)src, bd.lw_lane);
+        v = ((v >> bd.lw_shift) & 0xFFFFu) * 0x10001u;
+        p0 = bsel(bd.mR0, v, p0);
+        p1 = bsel(bd.mR1, v, p1);
+    }
+}
+
+__device__ __forceinline__ uint32_t load_px4(const uint8_t* row, int c0, int W, bool fast) {
+    if (fast) return *reinterpret_cast<const uint32_t*>(row + c0);
+    uint32_t v = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        int c = min(max(c0 + k, 0), W - 1);
+        v |= (uint32_t)row[c] << (8 * k);
+    }
+    return v;
+}
+
+// Horizontal 5-tap binomial of the lane's 4 pixels (needs 2 from each side).
+__device__ __forceinline__ void hblur(uint32_t d, uint32_t& h0, uint32_t& h1) {
+    const uint32_t dl = from_left(d), dr = from_right(d);
+    const u16x2 Em1 = U(perm(0u, dl, 0x0C030C02u));  // (c0-2, c0-1)
+    const u16x2 E0 = U(perm(0u, d, 0x0C010C00u));    // (c0,   c0+1)
+    const u16x2 E1 = U(perm(0u, d, 0x0C030C02u));    // (c0+2, c0+3)
+    const u16x2 E2 = U(perm(0u, dr, 0x0C010C00u));   // (c0+4, c0+5)
+    const u16x2 Om1 = U(perm(d, dl, 0x0C040C03u));   // (c0-1, c0)
+    const u16x2 O0 = U(perm(0u, d, 0x0C020C01u));    // (c0+1, c0+2)
+    const u16x2 O1 = U(perm(dr, d, 0x0C040C03u));    // (c0+3, c0+4)
+    const u16x2 four = {4, 4}, six = {6, 6};
+    h0 = W32((Em1 + E1) + (Om1 + O0) * four + E0 * six);
+    h1 = W32((E0 + E2) + (O0 + O1) * four + E1 * six);
+}
+
+// One row of strength with its column-shifted copies, per lane:
+// c0 = (x, x+1), c1 = (x+2, x+3), sm1 = (x-1, x), s1 = (x+1, x+2), s3 = (x+3, x+4).
+struct MRow {
+    uint32_t c0, c1, sm1, s1, s3;
+};
+// Direction masks of one row (16-bit all-ones / all-zeros per pixel).
+struct DirRow {
+    uint32_t h0, h1, v0, v1, dm0, dm1;
+};
+
+__device__ __forceinline__ MRow msel(bool p, const MRow& a, const MRow& b) {
+    MRow r;
+    r.c0 = p ? a.c0 : b.c0; r.c1 = p ? a.c1 : b.c1;
+    r.sm1 = p ? a.sm1 : b.sm1; r.s1 = p ? a.s1 : b.s1; r.s3 = p ? a.s3 : b.s3;
+    return r;
+}
+
+__device__ __forceinline__ DirRow direction_masks(i16x2 gx0, i16x2 gx1, i16x2 gy0, i16x2 gy1,
+                                                  i16x2 ax0, i16x2 ax1, i16x2 ay0, i16x2 ay1) {
+    const i16x2 kH = {408, -169}, kV = {-169, 408};
+    const uint32_t q00 = perm(W32(ax0), W32(ay0), 0x05040100u);  // (|Gy|, |Gx|) of x
+    const uint32_t q01 = perm(W32(ax0), W32(ay0), 0x07060302u);  // (|Gy|, |Gx|) of x+1
+    const uint32_t q10 = perm(W32(ax1), W32(ay1), 0x05040100u);
+    const uint32_t q11 = perm(W32(ax1), W32(ay1), 0x07060302u);
+    const int h00 = __builtin_amdgcn_sdot2(S(q00), kH, 0, false);
+    const int h01 = __builtin_amdgcn_sdot2(S(q01), kH, 0, false);
+    const int h10 = __builtin_amdgcn_sdot2(S(q10), kH, 0, false);
+    const int h11 = __builtin_amdgcn_sdot2(S(q11), kH, 0, false);
+    const int v00 = __builtin_amdgcn_sdot2(S(q00), kV, 0, false);
+    const int v01 = __builtin_amdgcn_sdot2(S(q01), kV, 0, false);
+    const int v10 = __builtin_amdgcn_sdot2(S(q10), kV, 0, false);
+    const int v11 = __builtin_amdgcn_sdot2(S(q11), kV, 0, false);
+    DirRow d;
+    // sign of each dot product -> a 16-bit mask (low half from the first pixel)
+    d.h0 = perm((uint32_t)h01, (uint32_t)h00, 0x0B0B0909u);
+    d.h1 = perm((uint32_t)h11, (uint32_t)h10, 0x0B0B0909u);
+    d.v0 = perm((uint32_t)v01, (uint32_t)v00, 0x0B0B0909u);
+    d.v1 = perm((uint32_t)v11, (uint32_t)v10, 0x0B0B0909u);
+    // anti-diagonal iff Gx and Gy have opposite signs
+    d.dm0 = perm(0u, W32(gx0 ^ gy0), 0x09090808u);
+    d.dm1 = perm(0u, W32(gx1 ^ gy1), 0x09090808u);
+    return d;
+}
+
+// Suppression + thresholds for one lane's 4 pixels -> packed 2-bit byte.
+__device__ __forceinline__ uint32_t classify4(const MRow& Mu, const MRow& Mc, const MRow& Md,
+                                              const DirRow& dr, uint32_t low2, uint32_t high2,
+                                              uint32_t vmask0, uint32_t vmask1) {
+    uint32_t code[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const uint32_t mc = j ? Mc.c1 : Mc.c0;
+        const uint32_t c_xm1 = j ? Mc.s1 : Mc.sm1, c_xp1 = j ? Mc.s3 : Mc.s1;
+        const uint32_t u_c = j ? Mu.c1 : Mu.c0;
+        const uint32_t u_xm1 = j ? Mu.s1 : Mu.sm1, u_xp1 = j ? Mu.s3 : Mu.s1;
+        const uint32_t d_c = j ? Md.c1 : Md.c0;
+        const uint32_t d_xm1 = j ? Md.s1 : Md.sm1, d_xp1 = j ? Md.s3 : Md.s1;
+        const uint32_t mh = j ? dr.h1 : dr.h0, mv = j ? dr.v1 : dr.v0, mdm = j ? dr.dm1 : dr.dm0;
+        // neighbour behind (p - d) and ahead (p + d) along the direction
+        const uint32_t back = bsel(mh, c_xm1, bsel(mv, u_c, bsel(mdm, u_xp1, u_xm1)));
+        const uint32_t fwd = bsel(mh, c_xp1, bsel(mv, d_c, bsel(mdm, d_xm1, d_xp1)));
+        const uint32_t gt_back = W32(S(back) - S(mc));  // sign set iff M > back
+        const uint32_t lt_fwd = W32(S(mc) - S(fwd));    // sign set iff M < fwd
+        const uint32_t keep = gt_back & ~lt_fwd;
+        const uint32_t strong = keep & W32(S(high2) - S(mc));  // M > high
+        const uint32_t cand = keep & ~W32(S(mc) - S(low2));    // M >= low
+        const u16x2 sh = {15, 15};
+        code[j] = W32((U(cand) >> sh) + (U(strong) >> sh)) & (j ? vmask1 : vmask0);
+    }
+    const uint32_t z = code[0] | (code[1] << 4);
+    return (z | (z >> 14)) & 0xFFu;
+}
+
+// The strip walk.  BORDER = false: every row and column the wave touches is
+// inside the image and the input is 4-byte aligned, so no clamping or
+// re-extension is needed.  BORDER = true: clamped loads and per-stage
+// replication of the edge row / column.
+template <int R, bool BORDER>
+__device__ __forceinline__ void walk(const U8FwdArgs& a, int X0, int Y0, int lane, bool fast_ok) {
+    const int H = a.H, W = a.W;
+    const int c0 = X0 - 4 + 4 * lane;
+
+    Border bd;
+    uint32_t vmask0 = 0xFFFFFFFFu, vmask1 = 0xFFFFFFFFu;
+    bool fast = true;
+    if (BORDER) {
+        bd.left = X0 == 0;
+        bd.right = X0 + kU8StripCols + 4 > W;
+        bd.l0_lane = 1;
+        const int off = W - 1 - (X0 - 4);  // position of column W-1 in the strip
+        bd.lw_lane = min(off >> 2, kWave - 1);
+        bd.lw_pair = (off >> 1) & 1;
+        bd.lw_shift = (off & 1) * 16;
+        bd.mL0 = (c0 < 0 ? 0xFFFFu : 0u) | (c0 + 1 < 0 ? 0xFFFF0000u : 0u);
+        bd.mL1 = (c0 + 2 < 0 ? 0xFFFFu : 0u) | (c0 + 3 < 0 ? 0xFFFF0000u : 0u);
+        bd.mR0 = (c0 >= W ? 0xFFFFu : 0u) | (c0 + 1 >= W ? 0xFFFF0000u : 0u);
+        bd.mR1 = (c0 + 2 >= W ? 0xFFFFu : 0u) | (c0 + 3 >= W ? 0xFFFF0000u : 0u);
+        vmask0 = ~bd.mR0;  // output columns inside the image
+        vmask1 = ~bd.mR1;
+        fast = fast_ok && c0 >= 0 && c0 + 4 <= W;
+    }
+    const uint32_t low2 = ((uint32_t)a.low & 0xFFFFu) * 0x10001u;
+    const uint32_t high2 = ((uint32_t)a.high & 0xFFFFu) * 0x10001u;
+    const bool store_lane = lane >= 1 && lane <= 62 && (!BORDER || c0 < W);
+    const uint32_t cls_off = (uint32_t)(c0 >> 2);  // only used by storing lanes (c0 >= 0)
+
+    // input rows are loaded kPF rows ahead of their use (a rolling queue)
+    constexpr int kPF = 12;
+    auto load_row = [&](int i) -> uint32_t {
+        if (BORDER) {
+            const int y = min(max(Y0 - 4 + i, 0), H - 1);
+            return load_px4(a.in + (int64_t)y * a.pitch, c0, W, fast);
+        }
+        const uint8_t* rowp = uniform_ptr(a.in + (int64_t)(Y0 - 4 + i) * a.pitch);
+        return *reinterpret_cast<const uint32_t*>(rowp + (uint32_t)c0);
+    };
+    uint32_t q[kPF];
+#pragma unroll
+    for (int i = 0; i < kPF; ++i) q[i] = i < R + 8 ? load_row(i) : 0u;
+
+    uint32_t hw0[5], hw1[5];                      // h rows vi-4 .. vi
+    uint32_t dxw0[3], dxw1[3], sxw0[3], sxw1[3];  // rows b-2 .. b
+    MRow mu, mc, md;                              // rows g-2, g-1, g
+    DirRow dir_prev, dir_cur;                     // rows g-1, g
+
+#pragma unroll
+    for (int i = 0; i < R + 8; ++i) {
+        // ---- Step 1a: horizontal blur of input row vi = Y0 - 4 + i
+#pragma unroll
+        for (int k = 0; k < 4; ++k) { hw0[k] = hw0[k + 1]; hw1[k] = hw1[k + 1]; }
+        const uint32_t cur = q[0];
+#pragma unroll
+        for (int k = 0; k < kPF - 1; ++k) q[k] = q[k + 1];
+        q[kPF - 1] = i + kPF < R + 8 ? load_row(i + kPF) : 0u;
+        hblur(cur, hw0[4], hw1[4]);
+        if (i < 4) continue;
+
+        // ---- Step 1b: vertical blur, B row b = vi - 2
+        const int b = Y0 - 6 + i;
+        const u16x2 four = {4, 4}, six = {6, 6}, rnd = {128, 128}, eight = {8, 8};
+        uint32_t B0 = W32(((U(hw0[0]) + U(hw0[4])) + (U(hw0[1]) + U(hw0[3])) * four +
+                           U(hw0[2]) * six + rnd) >> eight);
+        uint32_t B1 = W32(((U(hw1[0]) + U(hw1[4])) + (U(hw1[1]) + U(hw1[3])) * four +
+                           U(hw1[2]) * six + rnd) >> eight);
+        if (BORDER) fix_cols(B0, B1, bd);
+        // Sobel row terms
+        const uint32_t bl = from_left(B1), br = from_right(B0);
+        const uint32_t Sm1 = align16(B0, bl), S1 = align16(B1, B0), S3 = align16(br, B1);
+        const u16x2 two = {2, 2};
+        uint32_t dx0 = W32(S(S1) - S(Sm1)), dx1 = W32(S(S3) - S(S1));
+        uint32_t sx0 = W32(U(Sm1) + U(S1) + U(B0) * two), sx1 = W32(U(S1) + U(S3) + U(B1) * two);
+        dxw0[0] = dxw0[1]; dxw0[1] = dxw0[2];
+        dxw1[0] = dxw1[1]; dxw1[1] = dxw1[2];
+        sxw0[0] = sxw0[1]; sxw0[1] = sxw0[2];
+        sxw1[0] = sxw1[1]; sxw1[1] = sxw1[2];
+        if (BORDER && b >= H) {  // rows below the image replicate row H-1
+            dx0 = dxw0[1]; dx1 = dxw1[1]; sx0 = sxw0[1]; sx1 = sxw1[1];
+        }
+        dxw0[2] = dx0; dxw1[2] = dx1; sxw0[2] = sx0; sxw1[2] = sx1;
+        if (BORDER && b == 0) {  // rows above the image replicate row 0
+            dxw0[0] = dxw0[1] = dx0; dxw1[0] = dxw1[1] = dx1;
+            sxw0[0] = sxw0[1] = sx0; sxw1[0] = sxw1[1] = sx1;
+        }
+        if (i < 6) continue;
+
+        // ---- Step 2: gradients, strength and direction of row g = b - 1
+        const int g = b - 1;
+        const i16x2 gx0 = S(dxw0[0]) + S(dxw0[1]) * (i16x2){2, 2} + S(dxw0[2]);
+        const i16x2 gx1 = S(dxw1[0]) + S(dxw1[1]) * (i16x2){2, 2} + S(dxw1[2]);
+        const i16x2 gy0 = S(sxw0[2]) - S(sxw0[0]);
+        const i16x2 gy1 = S(sxw1[2]) - S(sxw1[0]);
+        const i16x2 ax0 = __builtin_elementwise_max(gx0, -gx0);
+        const i16x2 ax1 = __builtin_elementwise_max(gx1, -gx1);
+        const i16x2 ay0 = __builtin_elementwise_max(gy0, -gy0);
+        const i16x2 ay1 = __builtin_elementwise_max(gy1, -gy1);
+        uint32_t M0 = W32(U(W32(ax0)) + U(W32(ay0)));
+        uint32_t M1 = W32(U(W32(ax1)) + U(W32(ay1)));
+        dir_prev = dir_cur;
+        dir_cur = direction_masks(gx0, gx1, gy0, gy1, ax0, ax1, ay0, ay1);
+
+        if (BORDER) fix_cols(M0, M1, bd);
+        MRow m;
+        m.c0 = M0;
+        m.c1 = M1;
+        {
+            const uint32_t ml = from_left(M1), mr = from_right(M0);
+            m.sm1 = align16(M0, ml);
+            m.s1 = align16(M1, M0);
+            m.s3 = align16(mr, M1);
+        }
+        mu = mc;
+        mc = md;
+        if (BORDER) {
+            md = msel(g >= H, mc, m);  // rows below the image replicate row H-1
+            if (g == 0) { mu = m; mc = m; }  // rows above replicate row 0
+        } else {
+            md = m;
+        }
+        if (i < 8) continue;
+
+        // ---- Step 3 + thresholds: row n = g - 1
+        const int n = g - 1;
+        if (BORDER && n >= H) continue;
+        const uint32_t byte = classify4(mu, mc, md, dir_prev, low2, high2, vmask0, vmask1);
+        if (store_lane) uniform_ptr(a.cls + (int64_t)n * a.cpitch)[cls_off] = (uint8_t)byte;
+    }
+}
+
+template <int R>
+__global__ void __launch_bounds__(kWGThreads)
+k_u8_forward(U8FwdArgs a, int strips_x, int nwaves, int fast_ok) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave_in_wg = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wg = xcd_remap(blockIdx.x, gridDim.x);
+    const int wave = wg * kWavesPerWG + wave_in_wg;
+    if (wave >= nwaves) return;
+    const int strip = wave % strips_x;
+    const int blk = wave / strips_x;
+    const int X0 = strip * kU8StripCols;
+    const int Y0 = blk * R;
+    const bool interior = fast_ok && X0 >= 4 && X0 + kU8StripCols + 4 <= a.W && Y0 >= 4 &&
+                          Y0 + R + 4 <= a.H;
+    if (interior) walk<R, false>(a, X0, Y0, lane, true);
+    else walk<R, true>(a, X0, Y0, lane, fast_ok);
+}
+
+}  // namespace
+
+int u8_forward_supported_rows(int rows) {
+    return rows == 16 || rows == 32 || rows == 48 || rows == 64;
+}
+
+template <int R>
+static hipError_t launch_r(const U8FwdArgs& a, hipStream_t s) {
+    const int strips_x = ceil_div(a.W, kU8StripCols);
+    const int nwaves = strips_x * ceil_div(a.H, R);
+    const int nwg = ceil_div(nwaves, kWavesPerWG);
+    const int fast_ok = ((uintptr_t)a.in % 4 == 0) && (a.pitch % 4 == 0);
+    hipLaunchKernelGGL(k_u8_forward<R>, dim3(nwg), dim3(kWGThreads), 0, s, a, strips_x, nwaves,
+                       fast_ok);
+    return hipGetLastError();
+}
+
+hipError_t launch_u8_forward(const U8FwdArgs& a, int rows_per_wave, hipStream_t s) {
+    switch (rows_per_wave) {
+        case 16: return launch_r<16>(a, s);
+        case 48: return launch_r<48>(a, s);
+        case 64: return launch_r<64>(a, s);
+        default: return launch_r<32>(a, s);
+    }
+}
+
+}  // namespace canny

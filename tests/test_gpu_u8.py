@@ -1,0 +1,187 @@
+"""GPU parity for the integer path: class maps and edge maps bit-exact against
+the CPU oracle (paper Section 2.2.1, Steps 1-4), through the C ABI."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from helpers import pack_classes, unpack_classes
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def canny():
+    import paper_1710_07745_amd as m
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return m
+
+
+def run_u8(canny, img, low=40, high=100, pitch_pad=0, offset=0):
+    H, W = img.shape
+    if pitch_pad or offset:
+        buf = torch.zeros(H * (W + pitch_pad) + offset + 64, dtype=torch.uint8, device="cuda")
+        view = buf[offset:offset + H * (W + pitch_pad)].view(H, W + pitch_pad)[:, :W]
+        view.copy_(torch.from_numpy(img))
+        dev = view
+    else:
+        dev = torch.from_numpy(np.ascontiguousarray(img)).cuda()
+    edges, cls = canny.canny_u8(dev, low, high, return_classes=True)
+    torch.cuda.synchronize()
+    return edges.cpu().numpy(), unpack_classes(cls.cpu().numpy(), H, W)
+
+
+def check_exact(canny, img, low=40, high=100, **kw):
+    e, c = run_u8(canny, img, low, high, **kw)
+    oe, oc = oracle.canny_u8(img, low, high)
+    H, W = img.shape
+    bad = np.argwhere(c != oc)
+    assert bad.size == 0, f"class mismatch at {bad[:5].tolist()} (H={H}, W={W}) gpu={c[tuple(bad[0])]} oracle={oc[tuple(bad[0])]}"
+    if not np.array_equal(e, oe):
+        d = np.argwhere(e != oe)
+        info = [(int(y), int(x), int(y) % 64, int(x) % 64, int(e[y, x]), int(oe[y, x]), int(oc[y, x]))
+                for y, x in d[:12]]
+        raise AssertionError(f"edge mismatch (H={H}, W={W}): {len(d)} px, gpu-only "
+                             f"{int(((e > 0) & (oe == 0)).sum())}, oracle-only "
+                             f"{int(((e == 0) & (oe > 0)).sum())}; (y, x, y%64, x%64, gpu, oracle, class) {info}")
+    return oc
+
+
+def test_config0_512(canny):
+    """512x512 natural image, low 40 / high 100."""
+    oc = check_exact(canny, workloads.natural_u8(512, 512, seed=0))
+    assert (oc == 2).sum() > 100 and (oc == 1).sum() > 100
+
+
+@pytest.mark.parametrize("H", [1, 2, 3, 4, 5, 7, 8, 9, 13, 31, 32, 33, 36, 37, 40, 41])
+def test_small_sizes(canny, H):
+    for W in [1, 2, 3, 4, 5, 6, 7, 8, 9, 11, 16, 17, 31, 33, 40]:
+        img = workloads.natural_u8(H, W, seed=H * 64 + W)
+        check_exact(canny, img, 10, 40)
+
+
+@pytest.mark.parametrize("H,W", [(300, 517), (257, 249), (250, 251), (1000, 1001), (64, 1000), (1000, 3)])
+def test_ragged_multi_tile(canny, H, W):
+    check_exact(canny, workloads.natural_u8(H, W, seed=H + 7 * W))
+
+
+@pytest.mark.parametrize("pad,offset", [(3, 0), (1, 1), (64, 3), (4, 4)])
+def test_unaligned_pitch(canny, pad, offset):
+    check_exact(canny, workloads.natural_u8(123, 301, seed=5), pitch_pad=pad, offset=offset)
+
+
+def test_step_edge_golden(canny):
+    for D, expect_line in [(15, False), (16, False), (40, False), (41, False), (42, True), (120, True)]:
+        for transpose in (False, True):
+            img = np.full((24, 24), 100, np.uint8)
+            img[:, 12:] = 100 + D
+            if transpose:
+                img = img.T.copy()
+            e, _ = run_u8(canny, img)
+            exp = np.zeros((24, 24), np.uint8)
+            if expect_line:
+                if transpose:
+                    exp[11, :] = 255
+                else:
+                    exp[:, 11] = 255
+            assert np.array_equal(e, exp), (D, transpose)
+
+
+def test_degenerate(canny):
+    flat = np.full((70, 300), 9, np.uint8)
+    e, c = run_u8(canny, flat, 0, 0)
+    assert not e.any() and not c.any()
+    img = workloads.natural_u8(200, 260, seed=4)
+    for lo, hi in [(0, 0), (0, 2040), (40, 40), (2040, 2040), (3000, 5000), (0, 1)]:
+        check_exact(canny, img, lo, hi)
+
+
+def test_noise_only(canny):
+    rng = np.random.default_rng(1)
+    check_exact(canny, rng.integers(0, 256, (333, 444), dtype=np.uint8), 100, 400)
+
+
+def test_full_4096(canny):
+    """The 4096x4096 benchmark image, checked whole against the oracle."""
+    check_exact(canny, workloads.natural_u8(4096, 4096, seed=10))
+
+
+def test_invalid_arguments(canny):
+    img = torch.zeros((8, 8), dtype=torch.uint8, device="cuda")
+    with pytest.raises(canny.CannyError):
+        canny.canny_u8(img, 50, 10)  # low > high
+    with pytest.raises(canny.CannyError):
+        canny.canny_u8(img, -1, 10)
+    with pytest.raises(ValueError):
+        canny.canny_u8(img, 10, 20, workspace=torch.empty(3, dtype=torch.uint8, device="cuda"))
+
+
+# ---------------------------------------------------------------- hysteresis alone
+
+def run_hyst(canny, cls):
+    H, W = cls.shape
+    packed = torch.from_numpy(pack_classes(cls)).cuda()
+    e = canny.hysteresis(packed, H, W)
+    torch.cuda.synchronize()
+    return e.cpu().numpy()
+
+
+@pytest.mark.parametrize("h,w", [(3, 3), (3, 4)])
+def test_hysteresis_exhaustive_small(canny, h, w):
+    import itertools
+    maps = np.array(list(itertools.product((0, 1, 2), repeat=h * w)), np.uint8)
+    cols = int(np.ceil(np.sqrt(len(maps))))
+    rows = -(-len(maps) // cols)
+    big = np.zeros((rows * (h + 1), cols * (w + 1)), np.uint8)
+    for k, m in enumerate(maps):
+        r, c = divmod(k, cols)
+        big[r * (h + 1):r * (h + 1) + h, c * (w + 1):c * (w + 1) + w] = m.reshape(h, w)
+    assert np.array_equal(run_hyst(canny, big), oracle.hysteresis(big)[0])
+
+
+@pytest.mark.parametrize("H,W,p", [(1, 1, 0.5), (1, 300, 0.6), (300, 1, 0.6), (65, 65, 0.45),
+                                   (128, 64, 0.41), (1000, 1000, 0.41), (777, 1333, 0.5),
+                                   (2048, 2048, 0.38), (4096, 4096, 0.42)])
+def test_hysteresis_random(canny, H, W, p):
+    cls = workloads.random_classes(H, W, seed=H + W, p_weak=p, p_strong=0.002)
+    assert np.array_equal(run_hyst(canny, cls), oracle.hysteresis(cls)[0])
+
+
+def test_hysteresis_long_chain(canny):
+    """One weak spiral seeded at its outer end: the whole chain must be found."""
+    N = 2048
+    ys, xs = workloads.spiral_path(N, spacing=4)
+    cls = np.zeros((N, N), np.uint8)
+    cls[ys, xs] = 1
+    cls[ys[0], xs[0]] = 2
+    e = run_hyst(canny, cls)
+    oe, depth = oracle.hysteresis(cls)
+    assert depth > 100000
+    assert np.array_equal(e, oe)
+
+
+def test_spiral_stress_16384(canny):
+    """Hysteresis stress image, 16384x16384: class map checked on bands against
+    the oracle, edges bit-exact against breadth-first search on the GPU's
+    class map."""
+    N = 16384
+    img = workloads.spiral_u8(N, seed=5, noise_sigma=0.0)
+    dev = torch.from_numpy(img).cuda()
+    edges, cls = canny.canny_u8(dev, 40, 100, return_classes=True)
+    torch.cuda.synchronize()
+    c = unpack_classes(cls.cpu().numpy(), N, N)
+    e = edges.cpu().numpy()
+    del edges, cls, dev
+    for y0 in (0, 5000, N - 300):
+        y1 = min(N, y0 + 300)
+        a, b = max(0, y0 - 4), min(N, y1 + 4)
+        oc, _, _ = oracle.classify_u8(img[a:b], 40, 100)
+        lo, hi = y0 - a, y0 - a + (y1 - y0)
+        inner = slice(lo if y0 == 0 else lo, hi)
+        # rows 4 away from a cut edge see the same neighbourhood as in the full image
+        chk = np.s_[max(inner.start, 0 if a == 0 else 4):min(inner.stop, (b - a) if b == N else (b - a) - 4)]
+        assert np.array_equal(c[a:b][chk], oc[chk]), y0
+    oe, depth = oracle.hysteresis(c)
+    assert np.array_equal(e, oe)
+    assert depth > 1000000
