@@ -1,0 +1,224 @@
+#!/usr/bin/env python3
+"""Benchmark of the MI355X Canny edge detector (one GPU).
+
+Headline (the JSON line's `value`): float Canny -- Gaussian sigma=1.4 (7 taps),
+Sobel, L2 strength, continuous-direction suppression, thresholds 0.05 / 0.15
+of the largest strength, 8-connected hysteresis -- on a 4096x4096 fp32 image,
+in MPix/s.  One step = one full pass of the operator over one image.  Inputs
+are seeded synthetic images (value-noise shading + 40 step-edged shapes +
+noise, see workloads.py) already resident in HBM; the step rotates through
+enough distinct input/output buffers (> 256 MB) that the 256 MB Infinity Cache
+cannot hold them, so every step streams from HBM.
+
+Also reported (under "configs"): the integer pipeline at 4096^2 and on the
+16384^2 hysteresis stress image, the float pipeline at 7680x4320, the batched
+uneven-size plan against a per-image loop, and the differentiable front end
+forward + backward.  `roofline` describes the dominant kernel of the headline
+step (the float forward's classification pass) timed alone with HIP events on
+its own stream; `cpu_baseline` is the C oracle on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+MALL_BYTES = 256 << 20
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def timed(fn, steps, warmup, stream):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for _ in range(steps):
+        fn()
+    t1.record(stream)
+    torch.cuda.synchronize()
+    return t0.elapsed_time(t1) / steps  # ms per call
+
+
+def n_rot(bytes_per_set):
+    return max(2, -(-2 * MALL_BYTES // max(bytes_per_set, 1)))
+
+
+def bench_f32(canny, torch, H, W, steps, warmup, seed):
+    import numpy as np
+    import workloads
+    X = workloads.natural_u8(H, W, seed=seed).astype(np.float32)
+    k = n_rot(H * W * 5)
+    xs = [torch.from_numpy(X).cuda() for _ in range(k)]
+    es = [torch.empty((H, W), dtype=torch.uint8, device="cuda") for _ in range(k)]
+    ws = torch.empty(canny.f32_workspace_bytes(H, W), dtype=torch.uint8, device="cuda")
+    it = [0]
+
+    def step():
+        i = it[0] % k
+        it[0] += 1
+        canny.canny_f32(xs[i], 1.4, 3, 0.05, 0.15, True, edges=es[i], workspace=ws)
+
+    st = torch.cuda.current_stream()
+    ms = timed(step, steps, warmup, st)
+    return {"ms": ms, "mpix_s": H * W / (ms * 1e-3) / 1e6, "rot_buffers": k}, (xs, es, ws)
+
+
+def roofline_f32_pass_b(canny, torch, bufs, H, W, steps, warmup):
+    """The classification pass alone: absolute thresholds equal to the relative
+    ones make canny_f32 launch exactly that one kernel."""
+    xs, es, ws = bufs
+    _, mx = canny.canny_f32(xs[0], with_edges=False, return_max=True, workspace=ws)
+    m = float(mx.cpu()[0])
+    lo, hi = 0.05 * m, 0.15 * m
+    k = len(xs)
+    cls = [torch.empty((H, canny.class_pitch(W)), dtype=torch.uint8, device="cuda") for _ in range(k)]
+    s = torch.cuda.Stream()
+    it = [0]
+
+    def one():
+        i = it[0] % k
+        it[0] += 1
+        canny.canny_f32(xs[i], 1.4, 3, lo, hi, False, with_edges=False, workspace=ws)
+
+    with torch.cuda.stream(s):
+        ms = timed(one, steps, warmup, s)
+    alg = H * W * (4 + 0.25)
+    gbs = alg / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "k_f32_forward<3,32,true> (float classification pass, 4096x4096)",
+            "bytes_per_launch": alg, "avg_launch_us": round(ms * 1e3, 2)}
+
+
+def bench_u8(canny, torch, img, steps, warmup, label):
+    H, W = img.shape
+    k = n_rot(H * W * 2)
+    xs = [torch.from_numpy(img).cuda() for _ in range(k)]
+    es = [torch.empty((H, W), dtype=torch.uint8, device="cuda") for _ in range(k)]
+    ws = torch.empty(canny.u8_workspace_bytes(H, W), dtype=torch.uint8, device="cuda")
+    it = [0]
+
+    def full():
+        i = it[0] % k
+        it[0] += 1
+        canny.canny_u8(xs[i], 40, 100, edges=es[i], workspace=ws)
+
+    def fwd():
+        i = it[0] % k
+        it[0] += 1
+        canny.canny_u8(xs[i], 40, 100, with_edges=False, workspace=ws)
+
+    st = torch.cuda.current_stream()
+    ms = timed(full, steps, warmup, st)
+    msf = timed(fwd, steps, warmup, st)
+    out = {"workload": label, "ms": round(ms, 4), "mpix_s": round(H * W / (ms * 1e-3) / 1e6, 1),
+           "forward_ms": round(msf, 4),
+           "forward_mpix_s": round(H * W / (msf * 1e-3) / 1e6, 1),
+           "forward_hbm_frac": round(H * W * 1.25 / (msf * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    del xs, es, ws
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(seconds=10.0):
+    import numpy as np
+    import oracle
+    import workloads
+    X = workloads.natural_u8(4096, 4096, seed=1).astype(np.float32)
+    oracle.canny_f32(X)  # warm caches / page in
+    n, t0 = 0, time.perf_counter()
+    while True:
+        oracle.canny_f32(X)
+        n += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": round(n * 4096 * 4096 / dt / 1e6, 2), "unit": "MPix/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{n} runs of the fp64 float Canny oracle (single thread) on the 4096x4096 "
+                      f"benchmark image, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-extra", action="store_true", help="headline only")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1710_07745_amd as canny
+    torch.cuda.set_device(0)
+
+    log("headline: float Canny 4096x4096")
+    head, bufs = bench_f32(canny, torch, 4096, 4096, args.steps, args.warmup, seed=1)
+    roof = roofline_f32_pass_b(canny, torch, bufs, 4096, 4096, args.steps, args.warmup)
+    del bufs
+    torch.cuda.empty_cache()
+
+    configs = {}
+    if not args.no_extra:
+        import workloads
+        log("u8 4096x4096")
+        configs["u8_4096"] = bench_u8(canny, torch, workloads.natural_u8(4096, 4096, seed=10),
+                                      args.steps, args.warmup, "integer Canny, 4096x4096 uint8")
+        log("f32 7680x4320")
+        r, b = bench_f32(canny, torch, 4320, 7680, args.steps, args.warmup, seed=2)
+        del b
+        torch.cuda.empty_cache()
+        configs["f32_7680x4320"] = {"workload": "float Canny, 7680x4320 fp32",
+                                    "ms": round(r["ms"], 4), "mpix_s": round(r["mpix_s"], 1)}
+        log("u8 16384x16384 spiral")
+        configs["u8_16384_spiral"] = bench_u8(canny, torch, workloads.spiral_u8(16384, seed=5),
+                                              max(3, args.steps // 5), 2,
+                                              "integer Canny, 16384x16384 spiral stress image")
+        for name, fn in (("batch_256_uneven", "bench_batch"), ("mag_fwd_bwd_32x1024", "bench_mag")):
+            f = globals().get(fn)
+            if f is not None:
+                log(name)
+                configs[name] = f(canny, torch, args.steps, args.warmup)
+
+    cpu = None if args.no_cpu else cpu_baseline()
+    line = {
+        "metric": "Canny MPix/s at 4096² & batched uneven sizes; % HBM roofline; fwd+bwd MPix/s",
+        "value": round(head["mpix_s"], 1),
+        "unit": "MPix/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["ms"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "float Canny (sigma 1.4, 7 taps, L2, interpolated NMS, relative "
+                               "thresholds 0.05/0.15, hysteresis), one 4096x4096 fp32 image per step",
+                   "image": [4096, 4096], "rotating_buffers": head["rot_buffers"]},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "configs": configs,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

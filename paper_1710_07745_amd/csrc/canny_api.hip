@@ -28,9 +28,11 @@ bool device_ok() {
     return cached[dev] == 1;
 }
 
+// Sizes whose tile-rounded pixel count fits the 31-bit component names of
+// the hysteresis pass (e.g. 46000 x 46000).
 bool size_ok(int H, int W) {
     return H >= 1 && W >= 1 && H <= (1 << 20) && W <= (1 << 20) &&
-           (int64_t)H * W <= ((int64_t)1 << 34);
+           (int64_t)ceil_div(H, 64) * ceil_div(W, 64) * 4096 < ((int64_t)1 << 31);
 }
 
 static bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
@@ -181,6 +183,7 @@ int canny_f32(const float* in, int64_t in_pitch, int H, int W, float sigma, int 
     f.low = low;
     f.high = high;
     f.relative = relative ? 1 : 0;
+    f.use_range = (relative || max_out) ? 1 : 0;  // pass A runs and reduces the input range
     f.maxbits = reinterpret_cast<uint32_t*>(w);
     f.cls = class2 ? class2 : reinterpret_cast<uint8_t*>(w + 256);
     f.cpitch = class_pitch(W);

@@ -18,6 +18,13 @@
 // order-independent because the value is non-negative); pass B runs the full
 // walk and derives the thresholds from that word on the device.
 //
+// Accuracy: every stage before the strength is linear, and Sobel ignores a
+// constant offset, so the walk filters X - c instead of X, with c the
+// midpoint of the image's value range (min and max are reduced in pass A;
+// without pass A, the midpoint of the wave's first input row).  That halves
+// the magnitude the fp32 accumulations round at, and a constant image gives
+// exactly zero.
+//
 // Suppression interpolates along the continuous gradient direction: with
 // t = min(|Gx|,|Gy|) / max(|Gx|,|Gy|) and same = (Gx*Gy > 0),
 //   dominant x: ahead = lerp(M(y,x+1), same ? M(y+1,x+1) : M(y-1,x+1), t)
@@ -54,6 +61,26 @@ __device__ __forceinline__ float lane_ext(const F4& x, int e) {
     if (e < -4) return from_left_f(from_left_f(x.v[e + 8]));
     if (e < 8) return from_right_f(x.v[e - 4]);
     return from_right_f(from_right_f(x.v[e - 8]));
+}
+
+// float <-> unsigned code with the same order (for atomicMin / atomicMax)
+__device__ __forceinline__ uint32_t f2ord(float f) {
+    const uint32_t b = bc<uint32_t>(f);
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ __forceinline__ float ord2f(uint32_t o) {
+    return bc<float>((o & 0x80000000u) ? (o & 0x7FFFFFFFu) : ~o);
+}
+
+__device__ __forceinline__ float wave_min(float v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fminf(v, __shfl_xor(v, off));
+    return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
+    return v;
 }
 
 struct BorderF {
@@ -165,6 +192,29 @@ k_f32_forward(F32FwdArgs a, int strips_x, int nwaves, int fast_ok) {
 #pragma unroll
     for (int k = 0; k < NW; ++k) win[k] = (k >= 2 * R && k - 2 * R < NI) ? fetch(k - 2 * R) : F4{};
 
+    // offset c subtracted from every input value (see the file comment)
+    float off;
+    if (PASS_B && a.use_range) {
+        off = 0.5f * ord2f(a.maxbits[1]) + 0.5f * ord2f(a.maxbits[2]);
+    } else {
+        const F4& r0 = win[2 * R];
+        const float lo = wave_min(fminf(fminf(r0.v[0], r0.v[1]), fminf(r0.v[2], r0.v[3])));
+        const float hi = wave_max(fmaxf(fmaxf(r0.v[0], r0.v[1]), fmaxf(r0.v[2], r0.v[3])));
+        off = 0.5f * lo + 0.5f * hi;
+    }
+    off = bc<float>(__builtin_amdgcn_readfirstlane(bc<int>(off)));  // wave-uniform
+    float xmin = 3.402823466e38f, xmax = -3.402823466e38f;  // pass A: input range
+#pragma unroll
+    for (int k = 2 * R; k < NW; ++k) {
+        if (k - 2 * R < NI) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (!PASS_B) { xmin = fminf(xmin, win[k].v[q]); xmax = fmaxf(xmax, win[k].v[q]); }
+                win[k].v[q] -= off;
+            }
+        }
+    }
+
     F4 dxw[3], sxw[3];
     MRowF mw[3];
     F4 gxp, gyp, gxc, gyc;  // gradients of rows g-1 (prev) and g (cur)
@@ -175,7 +225,17 @@ k_f32_forward(F32FwdArgs a, int strips_x, int nwaves, int fast_ok) {
         if (i > 0) {
 #pragma unroll
             for (int k = 0; k < NW - 1; ++k) win[k] = win[k + 1];
-            win[NW - 1] = i + PF < NI ? fetch(i + PF) : F4{};
+            if (i + PF < NI) {
+                win[NW - 1] = fetch(i + PF);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (!PASS_B) {
+                        xmin = fminf(xmin, win[NW - 1].v[q]);
+                        xmax = fmaxf(xmax, win[NW - 1].v[q]);
+                    }
+                    win[NW - 1].v[q] -= off;
+                }
+            }
         }
         if (i < 2 * R) continue;
         // ---- Step 1: Gaussian, row b = vi - R (vertical taps, then horizontal)
@@ -298,12 +358,22 @@ k_f32_forward(F32FwdArgs a, int strips_x, int nwaves, int fast_ok) {
     if (!PASS_B) {
         uint32_t v = bc<uint32_t>(smax);
 #pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, off));
-        if (lane == 0 && v) atomicMax(a.maxbits, v);
+        for (int o = 32; o >= 1; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o));
+        const float wmin = wave_min(xmin), wmax = wave_max(xmax);
+        if (lane == 0) {
+            if (v) atomicMax(a.maxbits, v);
+            atomicMin(a.maxbits + 1, f2ord(wmin));
+            atomicMax(a.maxbits + 2, f2ord(wmax));
+        }
     }
 }
 
-__global__ void k_fill_u32(uint32_t* p, uint32_t v) { *p = v; }
+// resets the max-pass words: max M^2 = 0, min code = all ones, max code = 0
+__global__ void k_reset_range(uint32_t* p) {
+    p[0] = 0u;
+    p[1] = 0xFFFFFFFFu;
+    p[2] = 0u;
+}
 
 template <int R>
 hipError_t launch_radius(const F32FwdArgs& a, hipStream_t s) {
@@ -315,7 +385,7 @@ hipError_t launch_radius(const F32FwdArgs& a, hipStream_t s) {
     const int nwg = ceil_div(nwaves, kWavesPerWG);
     const int fast_ok = ((uintptr_t)a.in % 16 == 0) && (a.pitch % 4 == 0);
     if (a.relative || a.max_out) {
-        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, s, a.maxbits, 0u);
+        hipLaunchKernelGGL(k_reset_range, dim3(1), dim3(1), 0, s, a.maxbits);
         hipLaunchKernelGGL((k_f32_forward<R, RR, false>), dim3(nwg), dim3(kWGThreads), 0, s, a,
                            strips_x, nwaves, fast_ok);
     }

@@ -6,22 +6,29 @@
 // grow with the length of a propagation chain.
 //
 // The image is cut into 64-column x T-row tiles.  Four launches:
-//   1. local:  each workgroup labels its tile in LDS (union-find with
-//              atomicMin linking, roots = smallest pixel index), marks which
-//              local components hold a strong pixel, and names every
-//              component that touches the tile border by its smallest
-//              border slot.  It writes, per border pixel, the global id of
-//              its component (or -1), and initialises parent/flag for the
-//              component representatives.
+//   1. local:  each workgroup labels its tile in LDS.  Candidates in a row
+//              are linked into runs first; then only the unions that can
+//              join a run to the row above are made (a run's first pixel
+//              joins N, or NW and NE when N is empty; a later pixel joins NE
+//              only when N is empty) -- the same components as joining every
+//              8-neighbour, with about one union per run instead of four per
+//              pixel.  Links use atomicMin (roots = smallest pixel index) and
+//              the forest is flattened by pointer jumping.  A component is
+//              named globally by tile * 64T + its root.  The pass writes, per
+//              tile-border pixel, the global name of its component (or -1),
+//              initialises parent/flag for every component that touches the
+//              border (sparse arrays indexed by global name), and writes one
+//              16-bit record per pixel: bit 15 candidate, bit 14 component
+//              holds a strong pixel of this tile, bits 0..11 the local root.
 //   2. merge:  one thread per tile-border pixel on the right and bottom tile
 //              edges unions its component with the 8-connected candidates
 //              across the edge (global union-find, atomicMin linking).
-//   3. flags:  every representative finds its root (read-only walk), stores
-//              it in its own slot (flattening the forest) and ORs its strong
-//              flag into the root's.
-//   4. final:  each workgroup relabels its tile (same LDS pass as 1), lifts
-//              the global strong flags onto its border components and
-//              writes 255 / 0 per pixel.
+//   3. flags:  one thread per border slot finds its component's root
+//              (read-only walk), stores it (flattening the forest) and ORs the
+//              component's strong flag into the root's.
+//   4. final:  each workgroup gathers the root flags of its border
+//              components into LDS and turns the per-pixel records into
+//              255 / 0.
 // Border slots of a tile (clipped to the image): top row x -> x, bottom row
 // x -> 64 + x, left column y -> 128 + y, right column y -> 128 + T + y.
 #include "canny_internal.h"
@@ -37,20 +44,25 @@ struct Tile {
     static constexpr int kTPR = kHystCols / kPPT;      // threads per tile row
 };
 
-__device__ __forceinline__ int lds_find(volatile int* L, int x) {
-    int p = L[x];
-    while (p != x) {
-        x = p;
-        p = L[x];
+// find with path halving (each visited pointer is replaced by its grandparent,
+// an ancestor); used only while unions are running, before the pointer-jumping
+// flatten, so a halving store can never overwrite a finished root pointer
+__device__ __forceinline__ int lds_find_halve(volatile int* L, int x) {
+    while (true) {
+        const int p = L[x];
+        if (p == x) return x;
+        const int gp = L[p];
+        if (gp == p) return p;
+        L[x] = gp;
+        x = gp;
     }
-    return x;
 }
 
 __device__ __forceinline__ void lds_union(int* L, int a, int b) {
     volatile int* V = L;
     while (true) {
-        a = lds_find(V, a);
-        b = lds_find(V, b);
+        a = lds_find_halve(V, a);
+        b = lds_find_halve(V, b);
         if (a == b) return;
         if (a < b) { const int t = a; a = b; b = t; }
         const int old = atomicMin(&L[a], b);
@@ -101,25 +113,50 @@ __device__ __forceinline__ TileGeom tile_geom(int tile, int tiles_x, int H, int 
     return g;
 }
 
-// Load this thread's class codes and build the tile's LDS union-find.
-// On return L[i] is the root (smallest index) of pixel i's component, or -1.
-// codes: 2 bits per pixel of the thread's segment (bit 2k = pixel k).
+// Candidate and strong bits of a thread's class codes, compressed to one bit
+// per pixel (bit k = pixel k of the segment).
+__device__ __forceinline__ uint32_t compress2(uint32_t x) {  // keeps bits 0, 2, 4, ...
+    x &= 0x55555555u;
+    x = (x | (x >> 1)) & 0x33333333u;
+    x = (x | (x >> 2)) & 0x0F0F0F0Fu;
+    x = (x | (x >> 4)) & 0x00FF00FFu;
+    x = (x | (x >> 8)) & 0x0000FFFFu;
+    return x;
+}
+
+// column of the first pixel of the run that covers column c, given the row's
+// run-start bits S (bit c of S is set where a run begins)
+__device__ __forceinline__ int run_start(uint64_t S, int c) {
+    const uint64_t m = c >= 63 ? S : (S & ((2ull << c) - 1ull));
+    return 63 - __clzll((long long)m);
+}
+
+// Per-tile labelling state shared by the local pass.
 template <int T>
-__device__ __forceinline__ uint32_t tile_label(const uint8_t* cls, int64_t cpitch, int W,
-                                               const TileGeom& g, int* L) {
+struct TileLabel {
+    uint32_t cand, strong;  // this thread's segment, bit k = pixel k
+    uint64_t m, S;          // candidate and run-start bits of this thread's row
+};
+
+// Load this thread's class codes and label the tile's candidates in LDS:
+// afterwards L[r*64 + s] is the root (smallest index) of the component of
+// the run that starts at column s of row r; only run starts carry entries.
+// cm holds the 64-bit candidate mask of every tile row.
+template <int T>
+__device__ __forceinline__ TileLabel<T> tile_label(const uint8_t* cls, int64_t cpitch, int W,
+                                                   const TileGeom& g, int* L, uint64_t* cm) {
     using TL = Tile<T>;
+    static_assert(TL::kPPT == 16, "row masks assume 16-pixel segments");
     const int t = threadIdx.x;
     const int r = t / TL::kTPR;
-    const int cb = (t % TL::kTPR) * TL::kPPT;
+    const int seg = t % TL::kTPR;
+    const int cb = seg * TL::kPPT;
     uint32_t codes = 0;
     if (r < g.th) {
         const uint8_t* row = cls + (int64_t)(g.Y0 + r) * cpitch + ((g.X0 + cb) >> 2);
-        const int nbytes = TL::kPPT / 4;
         const int avail = (int)(cpitch - ((g.X0 + cb) >> 2));  // bytes left in the row
-        if (avail >= nbytes) {
-            if (nbytes == 4) codes = *reinterpret_cast<const uint32_t*>(row);
-            else if (nbytes == 2) codes = *reinterpret_cast<const uint16_t*>(row);
-            else codes = row[0];
+        if (avail >= 4) {
+            codes = *reinterpret_cast<const uint32_t*>(row);
         } else {
             for (int k = 0; k < avail; ++k) codes |= (uint32_t)row[k] << (8 * k);
         }
@@ -127,35 +164,58 @@ __device__ __forceinline__ uint32_t tile_label(const uint8_t* cls, int64_t cpitc
         const int valid = min(max(W - (g.X0 + cb), 0), TL::kPPT);
         if (valid < 16) codes &= (valid == 0) ? 0u : (0xFFFFFFFFu >> (32 - 2 * valid));
     }
-#pragma unroll
-    for (int k = 0; k < TL::kPPT; ++k) {
-        const int i = r * kHystCols + cb + k;
-        L[i] = ((codes >> (2 * k)) & 3u) ? i : -1;
+    TileLabel<T> st;
+    st.cand = compress2(codes | (codes >> 1));
+    st.strong = compress2((codes >> 1) & ~codes);  // code 2
+    reinterpret_cast<uint16_t*>(cm)[r * 4 + seg] = (uint16_t)st.cand;
+    __syncthreads();
+    st.m = cm[r];
+    st.S = st.m & ~(st.m << 1);
+    const uint64_t segmask = 0xFFFFull << cb;
+    const uint64_t Smine = st.S & segmask;
+    for (uint64_t b = Smine; b; b &= b - 1) {
+        const int i = r * kHystCols + __ffsll((long long)b) - 1;
+        L[i] = i;
     }
     __syncthreads();
-    if (r < g.th) {
-#pragma unroll
-        for (int k = 0; k < TL::kPPT; ++k) {
-            if (!((codes >> (2 * k)) & 3u)) continue;
-            const int c = cb + k;
-            const int i = r * kHystCols + c;
-            if (c > 0 && L[i - 1] >= 0) lds_union(L, i, i - 1);
-            if (r > 0) {
-                const int up = i - kHystCols;
-                if (c > 0 && L[up - 1] >= 0) lds_union(L, i, up - 1);
-                if (L[up] >= 0) lds_union(L, i, up);
-                if (c + 1 < kHystCols && L[up + 1] >= 0) lds_union(L, i, up + 1);
-            }
+    if (r > 0 && (st.m & segmask)) {  // runs may start in an earlier segment
+        const uint64_t A = cm[r - 1];
+        const uint64_t SA = A & ~(A << 1);
+        const int up = (r - 1) * kHystCols, me = r * kHystCols;
+        // a run joins the row above through its first pixel (N, or NW and NE
+        // when N is empty) and through any later pixel whose N is empty but NE
+        // is not; every other 8-neighbour is already in one of those runs
+        for (uint64_t b = st.S & A & segmask; b; b &= b - 1) {
+            const int c = __ffsll((long long)b) - 1;
+            lds_union(L, me + c, up + run_start(SA, c));
+        }
+        for (uint64_t b = st.S & ~A & (A << 1) & segmask; b; b &= b - 1) {
+            const int c = __ffsll((long long)b) - 1;
+            lds_union(L, me + run_start(st.S, c), up + run_start(SA, c - 1));
+        }
+        for (uint64_t b = st.m & ~A & (A >> 1) & segmask; b; b &= b - 1) {
+            const int c = __ffsll((long long)b) - 1;
+            lds_union(L, me + run_start(st.S, c), up + run_start(SA, c + 1));
         }
     }
     __syncthreads();
-#pragma unroll
-    for (int k = 0; k < TL::kPPT; ++k) {
-        const int i = r * kHystCols + cb + k;
-        if ((codes >> (2 * k)) & 3u) L[i] = lds_find(L, i);
+    // flatten the run starts by pointer jumping (each round at least halves
+    // every depth; the reads of one thread are independent)
+    volatile int* V = L;
+    while (true) {
+        bool changed = false;
+        for (uint64_t b = Smine; b; b &= b - 1) {
+            const int i = r * kHystCols + __ffsll((long long)b) - 1;
+            const int p = V[i];
+            const int q = V[p];
+            if (q != p) {
+                V[i] = q;
+                changed = true;
+            }
+        }
+        if (!__syncthreads_or(changed)) break;
     }
-    __syncthreads();
-    return codes;
+    return st;
 }
 
 // Visit the border slots of pixel (r, c) of a tile clipped to th x tw.
@@ -171,46 +231,54 @@ template <int T>
 __global__ void __launch_bounds__(kWGThreads) k_hyst_local(HystArgs a, int tiles_x) {
     using TL = Tile<T>;
     __shared__ int L[TL::kPx];
-    __shared__ int rep[TL::kPx];
-    __shared__ int sfl[TL::kPx];
-    __shared__ int bl[TL::kPerim];  // staged border labels: one global store per slot
+    __shared__ uint64_t cm[T];        // candidate mask of each tile row
+    __shared__ uint8_t sfl[TL::kPx];  // component (by root) holds a strong pixel
+    __shared__ int bl[TL::kPerim];    // staged border names: one global store per slot
     const TileGeom g = tile_geom<T>(blockIdx.x, tiles_x, a.H, a.W);
     const int t = threadIdx.x;
-    for (int i = t; i < TL::kPx; i += kWGThreads) { rep[i] = 0x7FFFFFFF; sfl[i] = 0; }
+    for (int i = t; i < TL::kPx / 4; i += kWGThreads) reinterpret_cast<uint32_t*>(sfl)[i] = 0u;
     for (int s = t; s < TL::kPerim; s += kWGThreads) bl[s] = -1;  // "no candidate"
-    const uint32_t codes = tile_label<T>(a.cls, a.cpitch, a.W, g, L);
+    const TileLabel<T> st = tile_label<T>(a.cls, a.cpitch, a.W, g, L, cm);
     const int r = t / TL::kTPR;
     const int cb = (t % TL::kTPR) * TL::kPPT;
+    const int me = r * kHystCols;
+    const int64_t gbase = (int64_t)g.tile * TL::kPx;
+    for (uint32_t b = st.strong; b; b &= b - 1) {
+        const int c = cb + __ffs(b) - 1;
+        sfl[L[me + run_start(st.S, c)]] = 1;
+    }
+    __syncthreads();
+    uint32_t rec[TL::kPPT];
+#pragma unroll
+    for (int k = 0; k < TL::kPPT; ++k) rec[k] = 0;
+    const bool edge_row = r == 0 || r == g.th - 1;
+    for (uint32_t b = st.cand; b; b &= b - 1) {
+        const int k = __ffs(b) - 1;
+        const int c = cb + k;
+        const int root = L[me + run_start(st.S, c)];
+        const int sf = sfl[root];
+        rec[k] = 0x8000u | (sf ? 0x4000u : 0u) | (uint32_t)root;
+        if (edge_row || c == 0 || c == g.tw - 1) {
+            const int64_t gid = gbase + root;
+            // every border pixel of the component stores the same values
+            a.parent[gid] = (int)gid;
+            a.flag[gid] = sf;
+            for_slots<T>(r, c, g.th, g.tw, [&](int s) { bl[s] = (int)gid; });
+        }
+    }
+    // records of the tile are contiguous: this thread's PPT pixels at t * PPT
+    uint16_t* dst = a.rec + gbase + t * TL::kPPT;
+#pragma unroll
+    for (int k = 0; k < TL::kPPT; k += 8) {
+        uint4 v;
+        v.x = rec[k] | rec[k + 1] << 16;
+        v.y = rec[k + 2] | rec[k + 3] << 16;
+        v.z = rec[k + 4] | rec[k + 5] << 16;
+        v.w = rec[k + 6] | rec[k + 7] << 16;
+        *reinterpret_cast<uint4*>(dst + k) = v;
+    }
+    __syncthreads();
     const int base = g.tile * TL::kPerim;
-    if (r < g.th) {
-#pragma unroll
-        for (int k = 0; k < TL::kPPT; ++k) {
-            const uint32_t code = (codes >> (2 * k)) & 3u;
-            if (!code) continue;
-            const int c = cb + k;
-            const int root = L[r * kHystCols + c];
-            if (code == 2) sfl[root] = 1;
-            for_slots<T>(r, c, g.th, g.tw, [&](int s) { atomicMin(&rep[root], s); });
-        }
-    }
-    __syncthreads();
-    if (r < g.th) {
-#pragma unroll
-        for (int k = 0; k < TL::kPPT; ++k) {
-            if (!((codes >> (2 * k)) & 3u)) continue;
-            const int c = cb + k;
-            const int root = L[r * kHystCols + c];
-            const int rs = rep[root];
-            for_slots<T>(r, c, g.th, g.tw, [&](int s) {
-                bl[s] = base + rs;
-                if (s == rs) {
-                    a.parent[base + s] = base + s;
-                    a.flag[base + s] = sfl[root];
-                }
-            });
-        }
-    }
-    __syncthreads();
     for (int s = t; s < TL::kPerim; s += kWGThreads) a.blab[base + s] = bl[s];
 }
 
@@ -256,75 +324,72 @@ template <int T>
 __global__ void __launch_bounds__(kWGThreads) k_hyst_flags(HystArgs a, int nslots) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= nslots) return;
-    if (a.blab[s] != s) return;  // not a component representative
-    // Read-only find; each thread then stores only its own slot, so every
-    // pointer another thread may follow is either its old value (an ancestor)
-    // or the root -- never a non-root written after the root.
-    int x = s;
+    const int gid = a.blab[s];
+    if (gid < 0) return;
+    // Read-only find; each thread then stores only the root into its
+    // component's entry (all threads of a component store the same value), so
+    // every pointer another thread may follow is either its old value (an
+    // ancestor) or the root -- never a non-root written after the root.
+    int x = gid;
     int p = a.parent[x];
     while (p != x) {
         x = p;
         p = a.parent[x];
     }
-    a.parent[s] = x;
-    if (a.flag[s]) a.flag[x] = 1;
+    a.parent[gid] = x;
+    if (a.flag[gid]) a.flag[x] = 1;
 }
 
 template <int T>
 __global__ void __launch_bounds__(kWGThreads) k_hyst_final(HystArgs a, int tiles_x, int vec16) {
     using TL = Tile<T>;
-    __shared__ int L[TL::kPx];
-    __shared__ int sfl[TL::kPx];
+    __shared__ uint8_t gflag[TL::kPx];  // global strong flag of border components, by local root
     const TileGeom g = tile_geom<T>(blockIdx.x, tiles_x, a.H, a.W);
     const int t = threadIdx.x;
-    for (int i = t; i < TL::kPx; i += kWGThreads) sfl[i] = 0;
-    const uint32_t codes = tile_label<T>(a.cls, a.cpitch, a.W, g, L);
+    const int base = g.tile * TL::kPerim;
+    const int64_t gbase = (int64_t)g.tile * TL::kPx;
+    for (int i = t; i < TL::kPx / 4; i += kWGThreads) reinterpret_cast<uint32_t*>(gflag)[i] = 0u;
+    __syncthreads();
+    for (int s = t; s < TL::kPerim; s += kWGThreads) {
+        const int gl = a.blab[base + s];
+        if (gl >= 0 && a.flag[a.parent[gl]]) gflag[gl - gbase] = 1;
+    }
     const int r = t / TL::kTPR;
     const int cb = (t % TL::kTPR) * TL::kPPT;
-    const int base = g.tile * TL::kPerim;
-    if (r < g.th) {
+    const uint16_t* src = a.rec + (int64_t)g.tile * TL::kPx + t * TL::kPPT;
+    uint32_t w[TL::kPPT / 2];
 #pragma unroll
-        for (int k = 0; k < TL::kPPT; ++k) {
-            const uint32_t code = (codes >> (2 * k)) & 3u;
-            if (!code) continue;
-            const int c = cb + k;
-            const int root = L[r * kHystCols + c];
-            if (code == 2) sfl[root] = 1;
-            for_slots<T>(r, c, g.th, g.tw, [&](int s) {
-                const int gl = a.blab[base + s];
-                if (gl == base + s) {  // this slot represents the component
-                    if (a.flag[a.parent[gl]]) sfl[root] = 1;
-                }
-            });
-        }
+    for (int k = 0; k < TL::kPPT; k += 8) {
+        const uint4 v = *reinterpret_cast<const uint4*>(src + k);
+        w[k / 2] = v.x; w[k / 2 + 1] = v.y; w[k / 2 + 2] = v.z; w[k / 2 + 3] = v.w;
     }
     __syncthreads();
-    if (r < g.th) {
-        uint8_t out[TL::kPPT];
+    if (r >= g.th) return;
+    uint8_t out[TL::kPPT];
 #pragma unroll
-        for (int k = 0; k < TL::kPPT; ++k) {
-            const uint32_t code = (codes >> (2 * k)) & 3u;
-            out[k] = (code && sfl[L[r * kHystCols + cb + k]]) ? 255 : 0;
-        }
-        uint8_t* dst = a.edges + (int64_t)(g.Y0 + r) * a.epitch + g.X0 + cb;
-        const int valid = min(a.W - (g.X0 + cb), TL::kPPT);
-        if (vec16 && valid == TL::kPPT) {
-            if constexpr (TL::kPPT == 16) {
-                uint4 v;
-                v.x = out[0] | out[1] << 8 | out[2] << 16 | (uint32_t)out[3] << 24;
-                v.y = out[4] | out[5] << 8 | out[6] << 16 | (uint32_t)out[7] << 24;
-                v.z = out[8] | out[9] << 8 | out[10] << 16 | (uint32_t)out[11] << 24;
-                v.w = out[12] | out[13] << 8 | out[14] << 16 | (uint32_t)out[15] << 24;
-                *reinterpret_cast<uint4*>(dst) = v;
-            } else {
-                uint2 v;
-                v.x = out[0] | out[1] << 8 | out[2] << 16 | (uint32_t)out[3] << 24;
-                v.y = out[4] | out[5] << 8 | out[6] << 16 | (uint32_t)out[7] << 24;
-                *reinterpret_cast<uint2*>(dst) = v;
-            }
+    for (int k = 0; k < TL::kPPT; ++k) {
+        const uint32_t q = (w[k / 2] >> (16 * (k & 1))) & 0xFFFFu;
+        const bool strong = (q & 0x4000u) || gflag[q & 0xFFFu];
+        out[k] = ((q & 0x8000u) && strong) ? 255 : 0;
+    }
+    uint8_t* dst = a.edges + (int64_t)(g.Y0 + r) * a.epitch + g.X0 + cb;
+    const int valid = min(a.W - (g.X0 + cb), TL::kPPT);
+    if (vec16 && valid == TL::kPPT) {
+        if constexpr (TL::kPPT == 16) {
+            uint4 v;
+            v.x = out[0] | out[1] << 8 | out[2] << 16 | (uint32_t)out[3] << 24;
+            v.y = out[4] | out[5] << 8 | out[6] << 16 | (uint32_t)out[7] << 24;
+            v.z = out[8] | out[9] << 8 | out[10] << 16 | (uint32_t)out[11] << 24;
+            v.w = out[12] | out[13] << 8 | out[14] << 16 | (uint32_t)out[15] << 24;
+            *reinterpret_cast<uint4*>(dst) = v;
         } else {
-            for (int k = 0; k < valid; ++k) dst[k] = out[k];
+            uint2 v;
+            v.x = out[0] | out[1] << 8 | out[2] << 16 | (uint32_t)out[3] << 24;
+            v.y = out[4] | out[5] << 8 | out[6] << 16 | (uint32_t)out[7] << 24;
+            *reinterpret_cast<uint2*>(dst) = v;
         }
+    } else {
+        for (int k = 0; k < valid; ++k) dst[k] = out[k];
     }
 }
 
@@ -352,23 +417,31 @@ int hyst_tile_rows_default() { return 64; }
 
 static int perim(int tile_rows) { return 2 * kHystCols + 2 * tile_rows; }
 
+static size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// blab: int32 per border slot; parent, flag: int32 per tile pixel (sparsely
+// touched: only entries named by a border component); rec: uint16 per pixel
 size_t hyst_workspace_bytes(int H, int W, int tile_rows) {
     const size_t ntiles = (size_t)ceil_div(W, kHystCols) * ceil_div(H, tile_rows);
-    const size_t nslots = ntiles * perim(tile_rows);
-    return 3 * ((nslots * sizeof(int32_t) + 255) & ~(size_t)255);
+    const size_t npx = ntiles * (size_t)kHystCols * tile_rows;
+    return al256(ntiles * perim(tile_rows) * 4) + 2 * al256(npx * 4) + al256(npx * 2);
 }
 
 void hyst_carve(void* ws, int H, int W, int tile_rows, HystArgs& a) {
     const size_t ntiles = (size_t)ceil_div(W, kHystCols) * ceil_div(H, tile_rows);
-    const size_t bytes = ((ntiles * perim(tile_rows) * sizeof(int32_t)) + 255) & ~(size_t)255;
+    const size_t npx = ntiles * (size_t)kHystCols * tile_rows;
     char* p = static_cast<char*>(ws);
     a.blab = reinterpret_cast<int32_t*>(p);
-    a.parent = reinterpret_cast<int32_t*>(p + bytes);
-    a.flag = reinterpret_cast<int32_t*>(p + 2 * bytes);
+    p += al256(ntiles * perim(tile_rows) * 4);
+    a.parent = reinterpret_cast<int32_t*>(p);
+    p += al256(npx * 4);
+    a.flag = reinterpret_cast<int32_t*>(p);
+    p += al256(npx * 4);
+    a.rec = reinterpret_cast<uint16_t*>(p);
 }
 
 hipError_t launch_hysteresis(const HystArgs& a, int tile_rows, hipStream_t s) {
-    if (tile_rows == 32) return launch_t<32>(a, s);
+    (void)tile_rows;  // 64-row tiles (16-pixel thread segments) only
     return launch_t<64>(a, s);
 }
 

@@ -83,9 +83,10 @@ struct HystArgs {
     int H, W;
     uint8_t* edges;
     int64_t epitch;
-    int32_t* blab;    // [ntiles * perim] border labels
-    int32_t* parent;  // [ntiles * perim] union-find forest over border labels
-    int32_t* flag;    // [ntiles * perim] strong flags
+    int32_t* blab;    // [ntiles * perim] global component name of each border pixel
+    int32_t* parent;  // [ntiles * 64T] union-find forest over component names (sparse)
+    int32_t* flag;    // [ntiles * 64T] strong flags (sparse)
+    uint16_t* rec;    // [ntiles * 64 * T] per-pixel records, tile-major
 };
 int hyst_tile_rows_default();
 size_t hyst_workspace_bytes(int H, int W, int tile_rows);
@@ -100,7 +101,9 @@ struct F32FwdArgs {
     int radius;
     float low, high;
     int relative;
-    uint32_t* maxbits;  // device scalar: float bits of max M (>= 0)
+    uint32_t* maxbits;  // device words: [0] float bits of max M^2 (>= 0),
+                        // [1] / [2] order-preserving codes of min / max input value
+    int use_range;      // pass B subtracts the midpoint of words [1], [2]
     uint8_t* cls;
     int64_t cpitch;
     float* mag;       // optional
