@@ -132,6 +132,35 @@ def bench_u8(canny, torch, img, steps, warmup, label):
     return out
 
 
+def bench_mag(canny, torch, steps, warmup):
+    """Differentiable front end: 32 images of 1024x1024 in [0, 1], sigma ~ U[1, 3],
+    radius 9; the loss gradient dM = 2 (M - T), T the magnitude at sigma = 2, is
+    formed once outside the timed region.  One step = forward + backward."""
+    import numpy as np
+    import workloads
+    N, H, W, R = 32, 1024, 1024, 9
+    I = torch.from_numpy(np.stack([workloads.natural_unit_f32(H, W, seed=2000 + i)
+                                   for i in range(N)])).cuda()
+    sig = torch.from_numpy(workloads.sigma_init(N, seed=4)).cuda()
+    T = canny.mag_forward(I, torch.full_like(sig, 2.0), R)
+    gM = 2.0 * (canny.mag_forward(I, sig, R) - T)
+    M = torch.empty_like(I)
+    st = torch.cuda.current_stream()
+    fwd = timed(lambda: canny.mag_forward(I, sig, R), steps, warmup, st)
+    bwd = timed(lambda: canny.mag_backward(I, sig, gM, R), steps, warmup, st)
+    both = timed(lambda: (canny.mag_forward(I, sig, R), canny.mag_backward(I, sig, gM, R)),
+                 steps, warmup, st)
+    px = N * H * W
+    del I, T, gM, M
+    torch.cuda.empty_cache()
+    return {"workload": "differentiable front end, 32 x 1024x1024 fp32, radius 9",
+            "fwd_ms": round(fwd, 4), "bwd_ms": round(bwd, 4), "fwd_bwd_ms": round(both, 4),
+            "fwd_mpix_s": round(px / (fwd * 1e-3) / 1e6, 1),
+            "bwd_mpix_s": round(px / (bwd * 1e-3) / 1e6, 1),
+            "fwd_bwd_mpix_s": round(px / (both * 1e-3) / 1e6, 1),
+            "fwd_bwd_hbm_frac": round(px * 20 / (both * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
 def cpu_baseline(seconds=10.0):
     import numpy as np
     import oracle

@@ -119,7 +119,7 @@ int canny_hysteresis(const uint8_t* class2, int H, int W, uint8_t* edges, int64_
  *         hysteresis as in the integer path.
  *
  * in          float H x W, pitch in_pitch floats.
- * sigma > 0, 1 <= radius <= 16, 0 <= low <= high.
+ * sigma > 0, 1 <= radius <= 8, 0 <= low <= high.
  * edges       uint8 output or NULL (class map only).
  * class2      optional class-map output or NULL.
  * mag_out     optional float H x W strength output (pitch W) or NULL.
@@ -171,14 +171,14 @@ void canny_batch_plan_destroy(canny_batch_plan* plan);
  * L2 strength), batched over N images of equal size, one sigma per image.
  *
  * canny_mag_forward: I float [N][H][W] contiguous, sigma float [N] (device),
- *   radius 1..16 fixed for all images (the taps are renormalised per
+ *   radius 1..12 fixed for all images (the taps are renormalised per
  *   sigma), M float [N][H][W] output.
  * canny_mag_backward: given dM = dL/dM [N][H][W], writes dL/dI
  *   [N][H][W] and dL/dsigma [N].  Replicate borders make each transposed
  *   stencil fold onto the edge pixels; dM/dG is taken as 0 where M = 0.  The
  *   blurred image is recomputed, not stored.  dsigma is reduced in a fixed
  *   order (run-to-run identical).  ws: canny_mag_backward_workspace_bytes.
- * Errors: NULL pointers, N, H, W < 1, radius outside 1..16 ->
+ * Errors: NULL pointers, N, H, W < 1, radius outside 1..12 ->
  *   CANNY_ERR_INVALID.  sigma values are read on the device; a sigma <= 0
  *   gives unspecified output (no fault).
  */

@@ -203,4 +203,39 @@ int canny_f32(const float* in, int64_t in_pitch, int H, int W, float sigma, int 
     return status_of(launch_hysteresis(h, T, s));
 }
 
+static bool mag_args_ok(const float* I, const float* sigma, int N, int H, int W, int radius) {
+    return I && sigma && N >= 1 && size_ok(H, W) && radius >= 1 && radius <= 12 &&
+           (int64_t)N * H * W <= ((int64_t)1 << 34);
+}
+
+int canny_mag_forward(const float* I, const float* sigma, int N, int H, int W, int radius, float* M,
+                      void* stream) {
+    if (!mag_args_ok(I, sigma, N, H, W, radius) || !M) return CANNY_ERR_INVALID;
+    const size_t n = (size_t)N * H * W * 4;
+    if (overlaps(I, n, M, n) || overlaps(sigma, (size_t)N * 4, M, n)) return CANNY_ERR_INVALID;
+    if (!device_ok()) return CANNY_ERR_UNSUPPORTED;
+    return status_of(launch_mag_forward(I, sigma, N, H, W, radius, M, static_cast<hipStream_t>(stream)));
+}
+
+size_t canny_mag_backward_workspace_bytes(int N, int H, int W, int radius) {
+    if (N < 1 || !size_ok(H, W) || radius < 1 || radius > 12) return 0;
+    return align256((size_t)N * H * W * 4) + align256(mag_partials(N, H, W, radius) * 4);
+}
+
+int canny_mag_backward(const float* I, const float* sigma, const float* dM, int N, int H, int W,
+                       int radius, float* dI, float* dsigma, void* ws, size_t ws_bytes, void* stream) {
+    if (!mag_args_ok(I, sigma, N, H, W, radius) || !dM || !dI || !dsigma) return CANNY_ERR_INVALID;
+    const size_t n = (size_t)N * H * W * 4;
+    if (overlaps(I, n, dI, n) || overlaps(dM, n, dI, n) || overlaps(dsigma, (size_t)N * 4, dI, n))
+        return CANNY_ERR_INVALID;
+    const size_t need = canny_mag_backward_workspace_bytes(N, H, W, radius);
+    if (!ws || ws_bytes < need || ((uintptr_t)ws % 256)) return CANNY_ERR_WORKSPACE;
+    if (!device_ok()) return CANNY_ERR_UNSUPPORTED;
+    char* w = static_cast<char*>(ws);
+    float* dB = reinterpret_cast<float*>(w);
+    float* partial = reinterpret_cast<float*>(w + align256(n));
+    return status_of(launch_mag_backward(I, sigma, dM, N, H, W, radius, dI, dsigma, dB, partial,
+                                         static_cast<hipStream_t>(stream)));
+}
+
 }  // extern "C"

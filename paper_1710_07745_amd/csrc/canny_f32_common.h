@@ -1,0 +1,91 @@
+// Shared pieces of the fp32 strip walks (Canny float forward and the
+// differentiable front end): a lane holds 4 adjacent columns of a row.
+#pragma once
+
+#include "canny_internal.h"
+
+namespace canny {
+namespace {
+
+struct F4 { float v[4]; };
+
+__device__ __forceinline__ F4 load_row(const float* row, int c0, int W, bool fast) {
+    F4 r;
+    if (fast) {
+        const float4 q = *reinterpret_cast<const float4*>(row + c0);
+        r.v[0] = q.x; r.v[1] = q.y; r.v[2] = q.z; r.v[3] = q.w;
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) r.v[k] = row[min(max(c0 + k, 0), W - 1)];
+    }
+    return r;
+}
+
+// value of a strip row at column offset e (relative to the lane's c0), for
+// e in [-16, 19]: own 4 values, up to 4 lanes to the left or right
+__device__ __forceinline__ float lane_ext(const F4& x, int e) {
+    if (e >= 0 && e < 4) return x.v[e];
+    if (e < 0) {
+        const int hops = (-e + 3) / 4;  // lanes to the left
+        float v = x.v[e + 4 * hops];
+        for (int h = 0; h < hops; ++h) v = from_left_f(v);
+        return v;
+    }
+    const int hops = e / 4;  // lanes to the right
+    float v = x.v[e - 4 * hops];
+    for (int h = 0; h < hops; ++h) v = from_right_f(v);
+    return v;
+}
+
+// float <-> unsigned code with the same order (for atomicMin / atomicMax)
+__device__ __forceinline__ uint32_t f2ord(float f) {
+    const uint32_t b = bc<uint32_t>(f);
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ __forceinline__ float ord2f(uint32_t o) {
+    return bc<float>((o & 0x80000000u) ? (o & 0x7FFFFFFFu) : ~o);
+}
+
+__device__ __forceinline__ float wave_min(float v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fminf(v, __shfl_xor(v, off));
+    return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
+    return v;
+}
+
+struct BorderF {
+    bool left, right;
+    int l0_lane;
+    int lw_lane, lw_px;
+    bool outL[4], outR[4];
+};
+
+__device__ __forceinline__ void fix_cols(F4& x, const BorderF& bd) {
+    if (bd.left) {
+        const float v = bc<float>(__builtin_amdgcn_readlane(bc<int>(x.v[0]), bd.l0_lane));
+#pragma unroll
+        for (int k = 0; k < 4; ++k) x.v[k] = bd.outL[k] ? v : x.v[k];
+    }
+    if (bd.right) {
+        float src = x.v[0];
+        if (bd.lw_px == 1) src = x.v[1];
+        if (bd.lw_px == 2) src = x.v[2];
+        if (bd.lw_px == 3) src = x.v[3];
+        const float v = bc<float>(__builtin_amdgcn_readlane(bc<int>(src), bd.lw_lane));
+#pragma unroll
+        for (int k = 0; k < 4; ++k) x.v[k] = bd.outR[k] ? v : x.v[k];
+    }
+}
+
+__device__ __forceinline__ F4 sel4(bool p, const F4& a, const F4& b) {
+    F4 r;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) r.v[k] = p ? a.v[k] : b.v[k];
+    return r;
+}
+}  // namespace
+}  // namespace canny

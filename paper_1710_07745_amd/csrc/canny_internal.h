@@ -111,4 +111,11 @@ struct F32FwdArgs {
 };
 hipError_t launch_f32_forward(const F32FwdArgs& a, hipStream_t s);
 
+size_t mag_partials(int N, int H, int W, int radius);
+hipError_t launch_mag_forward(const float* I, const float* sigma, int N, int H, int W, int radius,
+                              float* M, hipStream_t s);
+hipError_t launch_mag_backward(const float* I, const float* sigma, const float* dM, int N, int H, int W,
+                               int radius, float* dI, float* dsigma, float* dB, float* partial,
+                               hipStream_t s);
+
 }  // namespace canny
