@@ -161,6 +161,41 @@ def bench_mag(canny, torch, steps, warmup):
             "fwd_bwd_hbm_frac": round(px * 20 / (both * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
+def bench_batch(canny, torch, steps, warmup):
+    """256 uint8 images, H ~ U{240..2160}, W ~ U{320..3840}: one replay of the
+    autotuned batch plan (one HIP graph) against a host loop of canny_u8 over
+    the same images on one stream."""
+    import workloads
+    shapes = workloads.batch_shapes(256, seed=3)
+    dev = [torch.from_numpy(workloads.natural_u8(h, w, seed=1000 + i)).cuda()
+           for i, (h, w) in enumerate(shapes)]
+    outs = [torch.empty((h, w), dtype=torch.uint8, device="cuda") for h, w in shapes]
+    plan = canny.BatchPlan(shapes, 40, 100, autotune=True)
+    ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device="cuda")
+    st = torch.cuda.current_stream()
+    nb = max(3, steps // 5)
+    t_graph = timed(lambda: plan.run(dev, outs, ws), nb, max(1, warmup // 5), st)
+    hmax = max(h for h, _ in shapes)
+    wmax = max(w for _, w in shapes)
+    ws1 = torch.empty(canny.u8_workspace_bytes(hmax, wmax), dtype=torch.uint8, device="cuda")
+
+    def loop():
+        for x, e in zip(dev, outs):
+            canny.canny_u8(x, 40, 100, edges=e, workspace=ws1)
+
+    t_loop = timed(loop, nb, max(1, warmup // 5), st)
+    px = sum(h * w for h, w in shapes)
+    info = plan.info()
+    plan.close()
+    del dev, outs, ws, ws1
+    torch.cuda.empty_cache()
+    return {"workload": "batched integer Canny, 256 uneven uint8 images (%.0f MPix)" % (px / 1e6),
+            "graph_ms": round(t_graph, 4), "loop_ms": round(t_loop, 4),
+            "graph_mpix_s": round(px / (t_graph * 1e-3) / 1e6, 1),
+            "loop_mpix_s": round(px / (t_loop * 1e-3) / 1e6, 1),
+            "speedup_vs_loop": round(t_loop / t_graph, 3), "tuned": info}
+
+
 def cpu_baseline(seconds=10.0):
     import numpy as np
     import oracle

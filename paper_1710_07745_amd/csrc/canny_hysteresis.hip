@@ -48,7 +48,7 @@ struct Tile {
 // an ancestor); used only while unions are running, before the pointer-jumping
 // flatten, so a halving store can never overwrite a finished root pointer
 __device__ __forceinline__ int lds_find_halve(volatile int* L, int x) {
-    while (true) {
+    for (int steps = x; steps >= 0; --steps) {  // pointers decrease: at most x + 1 hops
         const int p = L[x];
         if (p == x) return x;
         const int gp = L[p];
@@ -56,11 +56,13 @@ __device__ __forceinline__ int lds_find_halve(volatile int* L, int x) {
         L[x] = gp;
         x = gp;
     }
+    return x;
 }
 
 __device__ __forceinline__ void lds_union(int* L, int a, int b) {
     volatile int* V = L;
-    while (true) {
+    // each retry follows a link that strictly lowers a, so a + 1 rounds suffice
+    for (int round = a > b ? a : b; round >= 0; --round) {
         a = lds_find_halve(V, a);
         b = lds_find_halve(V, b);
         if (a == b) return;
@@ -75,9 +77,11 @@ __device__ __forceinline__ int g_load(const int* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Parent pointers only ever point to smaller names, so a walk from x ends
+// within x + 1 steps; the bound makes that explicit.
 __device__ __forceinline__ int g_find(int* parent, int x) {
     int p = g_load(parent + x);
-    while (p != x) {
+    for (int steps = x; p != x && steps >= 0; --steps) {
         x = p;
         p = g_load(parent + x);
     }
@@ -85,7 +89,7 @@ __device__ __forceinline__ int g_find(int* parent, int x) {
 }
 
 __device__ __forceinline__ void g_union(int* parent, int a, int b) {
-    while (true) {
+    for (int round = a > b ? a : b; round >= 0; --round) {  // a strictly decreases per retry
         a = g_find(parent, a);
         b = g_find(parent, b);
         if (a == b) return;
@@ -202,7 +206,8 @@ __device__ __forceinline__ TileLabel<T> tile_label(const uint8_t* cls, int64_t c
     // flatten the run starts by pointer jumping (each round at least halves
     // every depth; the reads of one thread are independent)
     volatile int* V = L;
-    while (true) {
+    // depth <= 4096 halves each round: 13 rounds always suffice
+    for (int round = 0; round < 16; ++round) {
         bool changed = false;
         for (uint64_t b = Smine; b; b &= b - 1) {
             const int i = r * kHystCols + __ffsll((long long)b) - 1;
@@ -228,13 +233,22 @@ __device__ __forceinline__ void for_slots(int r, int c, int th, int tw, F f) {
 }
 
 template <int T>
-__global__ void __launch_bounds__(kWGThreads) k_hyst_local(HystArgs a, int tiles_x) {
+struct LocalSmem {
+    int L[Tile<T>::kPx];
+    uint64_t cm[T];               // candidate mask of each tile row
+    uint8_t sfl[Tile<T>::kPx];    // component (by root) holds a strong pixel
+    int bl[Tile<T>::kPerim];      // staged border names: one global store per slot
+};
+
+// Pass 1 on one tile (the whole workgroup takes part).
+template <int T>
+__device__ __forceinline__ void local_tile(const HystArgs& a, int tile, int tiles_x, LocalSmem<T>& sm) {
     using TL = Tile<T>;
-    __shared__ int L[TL::kPx];
-    __shared__ uint64_t cm[T];        // candidate mask of each tile row
-    __shared__ uint8_t sfl[TL::kPx];  // component (by root) holds a strong pixel
-    __shared__ int bl[TL::kPerim];    // staged border names: one global store per slot
-    const TileGeom g = tile_geom<T>(blockIdx.x, tiles_x, a.H, a.W);
+    int* L = sm.L;
+    uint64_t* cm = sm.cm;
+    uint8_t* sfl = sm.sfl;
+    int* bl = sm.bl;
+    const TileGeom g = tile_geom<T>(tile, tiles_x, a.H, a.W);
     const int t = threadIdx.x;
     for (int i = t; i < TL::kPx / 4; i += kWGThreads) reinterpret_cast<uint32_t*>(sfl)[i] = 0u;
     for (int s = t; s < TL::kPerim; s += kWGThreads) bl[s] = -1;  // "no candidate"
@@ -283,14 +297,16 @@ __global__ void __launch_bounds__(kWGThreads) k_hyst_local(HystArgs a, int tiles
 }
 
 template <int T>
-__global__ void __launch_bounds__(kWGThreads)
-k_hyst_merge(HystArgs a, int tiles_x, int tiles_y, int ntiles) {
+__global__ void __launch_bounds__(kWGThreads) k_hyst_local(HystArgs a, int tiles_x) {
+    __shared__ LocalSmem<T> sm;
+    local_tile<T>(a, blockIdx.x, tiles_x, sm);
+}
+
+// Pass 2 for border pixel k of a tile (k < T: right edge row k; else bottom
+// edge column k - T).
+template <int T>
+__device__ __forceinline__ void merge_one(const HystArgs& a, int tile, int k, int tiles_x, int tiles_y) {
     using TL = Tile<T>;
-    const int per_tile = T + kHystCols;
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= (int64_t)ntiles * per_tile) return;
-    const int tile = (int)(gid / per_tile);
-    const int k = (int)(gid - (int64_t)tile * per_tile);
     const TileGeom g = tile_geom<T>(tile, tiles_x, a.H, a.W);
     const int base = tile * TL::kPerim;
     if (k < T) {  // right tile edge: pixel (k, tw-1) against column X0+64
@@ -321,9 +337,17 @@ k_hyst_merge(HystArgs a, int tiles_x, int tiles_y, int ntiles) {
 }
 
 template <int T>
-__global__ void __launch_bounds__(kWGThreads) k_hyst_flags(HystArgs a, int nslots) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= nslots) return;
+__global__ void __launch_bounds__(kWGThreads)
+k_hyst_merge(HystArgs a, int tiles_x, int tiles_y, int ntiles) {
+    const int per_tile = T + kHystCols;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (int64_t)ntiles * per_tile) return;
+    const int tile = (int)(gid / per_tile);
+    merge_one<T>(a, tile, (int)(gid - (int64_t)tile * per_tile), tiles_x, tiles_y);
+}
+
+// Pass 3 for border slot s.
+__device__ __forceinline__ void flags_one(const HystArgs& a, int s) {
     const int gid = a.blab[s];
     if (gid < 0) return;
     // Read-only find; each thread then stores only the root into its
@@ -332,7 +356,7 @@ __global__ void __launch_bounds__(kWGThreads) k_hyst_flags(HystArgs a, int nslot
     // ancestor) or the root -- never a non-root written after the root.
     int x = gid;
     int p = a.parent[x];
-    while (p != x) {
+    for (int steps = gid; p != x && steps >= 0; --steps) {  // pointers decrease
         x = p;
         p = a.parent[x];
     }
@@ -340,11 +364,18 @@ __global__ void __launch_bounds__(kWGThreads) k_hyst_flags(HystArgs a, int nslot
     if (a.flag[gid]) a.flag[x] = 1;
 }
 
+__global__ void __launch_bounds__(kWGThreads) k_hyst_flags(HystArgs a, int nslots) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < nslots) flags_one(a, s);
+}
+
+// Pass 4 on one tile; gflag: LDS, global strong flag of border components by
+// local root.
 template <int T>
-__global__ void __launch_bounds__(kWGThreads) k_hyst_final(HystArgs a, int tiles_x, int vec16) {
+__device__ __forceinline__ void final_tile(const HystArgs& a, int tile, int tiles_x, int vec16,
+                                           uint8_t* gflag) {
     using TL = Tile<T>;
-    __shared__ uint8_t gflag[TL::kPx];  // global strong flag of border components, by local root
-    const TileGeom g = tile_geom<T>(blockIdx.x, tiles_x, a.H, a.W);
+    const TileGeom g = tile_geom<T>(tile, tiles_x, a.H, a.W);
     const int t = threadIdx.x;
     const int base = g.tile * TL::kPerim;
     const int64_t gbase = (int64_t)g.tile * TL::kPx;
@@ -364,7 +395,7 @@ __global__ void __launch_bounds__(kWGThreads) k_hyst_final(HystArgs a, int tiles
         w[k / 2] = v.x; w[k / 2 + 1] = v.y; w[k / 2 + 2] = v.z; w[k / 2 + 3] = v.w;
     }
     __syncthreads();
-    if (r >= g.th) return;
+    if (r >= g.th) return;  // no barrier follows in this function
     uint8_t out[TL::kPPT];
 #pragma unroll
     for (int k = 0; k < TL::kPPT; ++k) {
@@ -394,6 +425,12 @@ __global__ void __launch_bounds__(kWGThreads) k_hyst_final(HystArgs a, int tiles
 }
 
 template <int T>
+__global__ void __launch_bounds__(kWGThreads) k_hyst_final(HystArgs a, int tiles_x, int vec16) {
+    __shared__ uint8_t gflag[Tile<T>::kPx];
+    final_tile<T>(a, blockIdx.x, tiles_x, vec16, gflag);
+}
+
+template <int T>
 hipError_t launch_t(const HystArgs& a, hipStream_t s) {
     using TL = Tile<T>;
     const int tiles_x = ceil_div(a.W, kHystCols);
@@ -405,13 +442,110 @@ hipError_t launch_t(const HystArgs& a, hipStream_t s) {
     const int64_t nmerge = (int64_t)ntiles * (T + kHystCols);
     hipLaunchKernelGGL(k_hyst_merge<T>, dim3((unsigned)ceil_div64(nmerge, kWGThreads)),
                        dim3(kWGThreads), 0, s, a, tiles_x, tiles_y, ntiles);
-    hipLaunchKernelGGL(k_hyst_flags<T>, dim3(ceil_div(nslots, kWGThreads)), dim3(kWGThreads), 0, s,
+    hipLaunchKernelGGL(k_hyst_flags, dim3(ceil_div(nslots, kWGThreads)), dim3(kWGThreads), 0, s,
                        a, nslots);
     hipLaunchKernelGGL(k_hyst_final<T>, dim3(ntiles), dim3(kWGThreads), 0, s, a, tiles_x, vec16);
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------- batches
+__device__ __forceinline__ HystArgs batch_args(const BatchImage& im, char* ws) {
+    HystArgs a;
+    a.cls = reinterpret_cast<const uint8_t*>(ws + im.cls_off);
+    a.cpitch = im.cpitch;
+    a.H = im.H;
+    a.W = im.W;
+    a.edges = im.edges;
+    a.epitch = im.epitch;
+    a.blab = reinterpret_cast<int32_t*>(ws + im.blab_off);
+    a.parent = reinterpret_cast<int32_t*>(ws + im.parent_off);
+    a.flag = reinterpret_cast<int32_t*>(ws + im.flag_off);
+    a.rec = reinterpret_cast<uint16_t*>(ws + im.rec_off);
+    return a;
+}
+
+// last image whose running count (selected by Get) is <= v
+template <typename Get>
+__device__ __forceinline__ int batch_find(const BatchImage* imgs, int n, int v, Get get) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (get(imgs[mid]) <= v) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int T>
+__global__ void __launch_bounds__(kWGThreads)
+k_hyst_local_batch(const BatchImage* imgs, const BatchDev* hdr, uint32_t* counter) {
+    __shared__ LocalSmem<T> sm;
+    __shared__ int task_s;
+    const int n = hdr->n, total = hdr->total_tiles;
+    char* ws = hdr->ws;
+    for (int pass = 0; pass <= total; ++pass) {  // each pass claims a new tile
+        if (threadIdx.x == 0) task_s = (int)atomicAdd(counter, 1u);
+        __syncthreads();
+        const int task = task_s;
+        if (task >= total) break;
+        const int i = batch_find(imgs, n, task, [](const BatchImage& m) { return m.tile_base; });
+        const BatchImage& im = imgs[i];
+        local_tile<T>(batch_args(im, ws), task - im.tile_base, im.tiles_x, sm);
+        __syncthreads();  // LDS and task_s are reused by the next tile
+    }
+}
+
+template <int T>
+__global__ void __launch_bounds__(kWGThreads) k_hyst_merge_batch(const BatchImage* imgs, const BatchDev* hdr) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= hdr->total_merge) return;
+    const int i = batch_find(imgs, hdr->n, g, [](const BatchImage& m) { return m.merge_base; });
+    const BatchImage& im = imgs[i];
+    const int local = g - im.merge_base;
+    const int tile = local / (T + kHystCols);
+    merge_one<T>(batch_args(im, hdr->ws), tile, local - tile * (T + kHystCols), im.tiles_x, im.tiles_y);
+}
+
+__global__ void __launch_bounds__(kWGThreads) k_hyst_flags_batch(const BatchImage* imgs, const BatchDev* hdr) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= hdr->total_slots) return;
+    const int i = batch_find(imgs, hdr->n, g, [](const BatchImage& m) { return m.slot_base; });
+    flags_one(batch_args(imgs[i], hdr->ws), g - imgs[i].slot_base);
+}
+
+template <int T>
+__global__ void __launch_bounds__(kWGThreads)
+k_hyst_final_batch(const BatchImage* imgs, const BatchDev* hdr, uint32_t* counter) {
+    __shared__ uint8_t gflag[Tile<T>::kPx];
+    __shared__ int task_s;
+    const int n = hdr->n, total = hdr->total_tiles;
+    char* ws = hdr->ws;
+    for (int pass = 0; pass <= total; ++pass) {  // each pass claims a new tile
+        if (threadIdx.x == 0) task_s = (int)atomicAdd(counter, 1u);
+        __syncthreads();
+        const int task = task_s;
+        if (task >= total) break;
+        const int i = batch_find(imgs, n, task, [](const BatchImage& m) { return m.tile_base; });
+        const BatchImage& im = imgs[i];
+        const int vec16 = ((uintptr_t)im.edges % 16 == 0) && (im.epitch % 16 == 0);
+        final_tile<T>(batch_args(im, ws), task - im.tile_base, im.tiles_x, vec16, gflag);
+        __syncthreads();
+    }
+}
+
 }  // namespace
+
+hipError_t launch_hyst_batch(const BatchImage* imgs, const BatchDev* hdr, uint32_t* counters,
+                             int total_merge, int total_slots, int nwg, hipStream_t s) {
+    constexpr int T = 64;
+    hipLaunchKernelGGL(k_hyst_local_batch<T>, dim3(nwg), dim3(kWGThreads), 0, s, imgs, hdr, counters);
+    hipLaunchKernelGGL(k_hyst_merge_batch<T>, dim3(ceil_div(max(total_merge, 1), kWGThreads)),
+                       dim3(kWGThreads), 0, s, imgs, hdr);
+    hipLaunchKernelGGL(k_hyst_flags_batch, dim3(ceil_div(max(total_slots, 1), kWGThreads)),
+                       dim3(kWGThreads), 0, s, imgs, hdr);
+    hipLaunchKernelGGL(k_hyst_final_batch<T>, dim3(nwg), dim3(kWGThreads), 0, s, imgs, hdr, counters + 1);
+    return hipGetLastError();
+}
 
 int hyst_tile_rows_default() { return 64; }
 

@@ -111,6 +111,32 @@ struct F32FwdArgs {
 };
 hipError_t launch_f32_forward(const F32FwdArgs& a, hipStream_t s);
 
+// ---------------------------------------------------------------- batches
+// Per-image descriptor of a batch plan (device copy rewritten by every call:
+// caller pointers change, the layout does not).
+struct BatchImage {
+    const uint8_t* in;
+    int64_t pitch;
+    uint8_t* edges;
+    int64_t epitch;
+    int H, W;
+    int64_t cpitch;
+    int64_t cls_off, blab_off, parent_off, flag_off, rec_off;  // bytes into the workspace
+    int fwd_strips_x, fwd_base;  // forward wave tasks before this image
+    int tiles_x, tiles_y, tile_base;
+    int merge_base, slot_base;
+};
+struct BatchDev {
+    char* ws;
+    int n;
+    int low, high;
+    int total_fwd, total_tiles, total_merge, total_slots;
+};
+hipError_t launch_u8_forward_batch(const BatchImage* imgs, const BatchDev* hdr, uint32_t* counter,
+                                   int rows_per_wave, int nwg, hipStream_t s);
+hipError_t launch_hyst_batch(const BatchImage* imgs, const BatchDev* hdr, uint32_t* counters,
+                             int total_merge, int total_slots, int nwg, hipStream_t s);
+
 size_t mag_partials(int N, int H, int W, int radius);
 hipError_t launch_mag_forward(const float* I, const float* sigma, int N, int H, int W, int radius,
                               float* M, hipStream_t s);

@@ -326,7 +326,60 @@ k_u8_forward(U8FwdArgs a, int strips_x, int nwaves, int fast_ok) {
     else walk<R, true>(a, X0, Y0, lane, fast_ok);
 }
 
+// Persistent batch forward: each wave claims (image, strip, row block) tasks
+// from a device counter until every image of the batch is covered.
+template <int R>
+__global__ void __launch_bounds__(kWGThreads)
+k_u8_forward_batch(const BatchImage* imgs, const BatchDev* hdr, uint32_t* counter) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int n = hdr->n, total = hdr->total_fwd;
+    char* ws = hdr->ws;
+    // every pass claims a new task, so total + 1 passes always end the loop
+    for (int pass = 0; pass <= total; ++pass) {
+        uint32_t task = 0;
+        if (lane == 0) task = atomicAdd(counter, 1u);
+        const int tk = __builtin_amdgcn_readfirstlane((int)task);
+        if (tk >= total) break;
+        int lo = 0, hi = n - 1;  // last image whose first task is <= tk
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (imgs[mid].fwd_base <= tk) lo = mid;
+            else hi = mid - 1;
+        }
+        const BatchImage& im = imgs[lo];
+        U8FwdArgs a;
+        a.in = im.in;
+        a.pitch = im.pitch;
+        a.H = im.H;
+        a.W = im.W;
+        a.low = hdr->low;
+        a.high = hdr->high;
+        a.cls = reinterpret_cast<uint8_t*>(ws + im.cls_off);
+        a.cpitch = im.cpitch;
+        const int local = tk - im.fwd_base;
+        const int blk = local / im.fwd_strips_x;
+        const int X0 = (local - blk * im.fwd_strips_x) * kU8StripCols;
+        const int Y0 = blk * R;
+        const bool fast_ok = ((uintptr_t)a.in % 4 == 0) && (a.pitch % 4 == 0);
+        const bool interior = fast_ok && X0 >= 4 && X0 + kU8StripCols + 4 <= a.W && Y0 >= 4 &&
+                              Y0 + R + 4 <= a.H;
+        if (interior) walk<R, false>(a, X0, Y0, lane, true);
+        else walk<R, true>(a, X0, Y0, lane, fast_ok);
+    }
+}
+
 }  // namespace
+
+hipError_t launch_u8_forward_batch(const BatchImage* imgs, const BatchDev* hdr, uint32_t* counter,
+                                   int rows_per_wave, int nwg, hipStream_t s) {
+    switch (rows_per_wave) {
+        case 16: hipLaunchKernelGGL(k_u8_forward_batch<16>, dim3(nwg), dim3(kWGThreads), 0, s, imgs, hdr, counter); break;
+        case 48: hipLaunchKernelGGL(k_u8_forward_batch<48>, dim3(nwg), dim3(kWGThreads), 0, s, imgs, hdr, counter); break;
+        case 64: hipLaunchKernelGGL(k_u8_forward_batch<64>, dim3(nwg), dim3(kWGThreads), 0, s, imgs, hdr, counter); break;
+        default: hipLaunchKernelGGL(k_u8_forward_batch<32>, dim3(nwg), dim3(kWGThreads), 0, s, imgs, hdr, counter); break;
+    }
+    return hipGetLastError();
+}
 
 int u8_forward_supported_rows(int rows) {
     return rows == 16 || rows == 32 || rows == 48 || rows == 64;
