@@ -222,6 +222,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-extra", action="store_true", help="headline only")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--profile-roofline", action="store_true",
+                    help="only the roofline kernel (float classification pass, 4096^2) and a "
+                         "256 MiB device copy, for hardware-counter runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -231,6 +234,25 @@ def main():
     import torch
     import paper_1710_07745_amd as canny
     torch.cuda.set_device(0)
+
+    if args.profile_roofline:
+        import numpy as np
+        import workloads
+        X = torch.from_numpy(workloads.natural_u8(4096, 4096, seed=1).astype(np.float32)).cuda()
+        ws = torch.empty(canny.f32_workspace_bytes(4096, 4096), dtype=torch.uint8, device="cuda")
+        _, mx = canny.canny_f32(X, with_edges=False, return_max=True, workspace=ws)
+        m = float(mx.cpu()[0])
+        for _ in range(args.steps):
+            canny.canny_f32(X, 1.4, 3, 0.05 * m, 0.15 * m, False, with_edges=False, workspace=ws)
+        src = torch.empty(256 << 20, dtype=torch.uint8, device="cuda").fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(args.steps):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_roofline": "done", "copy_bytes": 256 << 20,
+                          "kernel_bytes": 4096 * 4096 * 4.25}), flush=True)
+        return
 
     log("headline: float Canny 4096x4096")
     head, bufs = bench_f32(canny, torch, 4096, 4096, args.steps, args.warmup, seed=1)
