@@ -14,8 +14,9 @@ Also reported (under "configs"): the integer pipeline at 4096^2 and on the
 16384^2 hysteresis stress image, the float pipeline at 7680x4320, the batched
 uneven-size plan against a per-image loop, and the differentiable front end
 forward + backward.  `roofline` describes the dominant kernel of the headline
-step (the float forward's classification pass) timed alone with HIP events on
-its own stream; `cpu_baseline` is the C oracle on the host.
+step (the float walk: blur, Sobel, strength, suppression), timed with HIP
+events that the library records around it on the step's stream;
+`cpu_baseline` is the C oracle on the host.
 """
 from __future__ import annotations
 
@@ -75,31 +76,37 @@ def bench_f32(canny, torch, H, W, steps, warmup, seed):
     return {"ms": ms, "mpix_s": H * W / (ms * 1e-3) / 1e6, "rot_buffers": k}, (xs, es, ws)
 
 
-def roofline_f32_pass_b(canny, torch, bufs, H, W, steps, warmup):
-    """The classification pass alone: absolute thresholds equal to the relative
-    ones make canny_f32 launch exactly that one kernel."""
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "f32_walk_4096_traffic.txt")
+
+
+def roofline_headline(canny, torch, bufs, H, W, steps):
+    """Per-stage device time of the headline step, from HIP events the library
+    records on the step's stream around each stage (a second pass over the
+    same rotating buffers, after the timed one).  The dominant kernel is the
+    float walk (Gaussian, Sobel, strength, suppression); its algorithmic bytes
+    are the float forward's 4 B/px in + 0.25 B/px of class map out."""
+    from paper_1710_07745_amd.profiling import read_traffic
     xs, es, ws = bufs
-    _, mx = canny.canny_f32(xs[0], with_edges=False, return_max=True, workspace=ws)
-    m = float(mx.cpu()[0])
-    lo, hi = 0.05 * m, 0.15 * m
     k = len(xs)
-    cls = [torch.empty((H, canny.class_pitch(W)), dtype=torch.uint8, device="cuda") for _ in range(k)]
-    s = torch.cuda.Stream()
-    it = [0]
-
-    def one():
-        i = it[0] % k
-        it[0] += 1
-        canny.canny_f32(xs[i], 1.4, 3, lo, hi, False, with_edges=False, workspace=ws)
-
-    with torch.cuda.stream(s):
-        ms = timed(one, steps, warmup, s)
+    with canny.StageTiming(steps) as t:
+        for i in range(steps):
+            canny.canny_f32(xs[i % k], 1.4, 3, 0.05, 0.15, True, edges=es[i % k], workspace=ws)
+        torch.cuda.synchronize()
+        us = {}
+        for name in ("f32_minmax", "f32_walk", "f32_classify", "hysteresis"):
+            ms, n = t.read(name)
+            us[name] = round(ms * 1e3 / max(n, 1), 2)
     alg = H * W * (4 + 0.25)
-    gbs = alg / (ms * 1e-3) / 1e9
+    walk_s = us["f32_walk"] * 1e-6
+    gbs = alg / walk_s / 1e9
+    fwd_s = (us["f32_minmax"] + us["f32_walk"] + us["f32_classify"]) * 1e-6
     return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": "k_f32_forward<3,32,true> (float classification pass, 4096x4096)",
-            "bytes_per_launch": alg, "avg_launch_us": round(ms * 1e3, 2)}
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": read_traffic(TRAFFIC_FILE),
+            "kernel": "k_f32_forward<3, 32, true> (float walk: blur, Sobel, strength, "
+                      "suppression; 4096x4096)",
+            "bytes_per_launch": alg, "avg_launch_us": us["f32_walk"],
+            "stage_avg_us": us,
+            "forward_frac": round(alg / fwd_s / 1e9 / HBM_PEAK_GBS, 4)}
 
 
 def bench_u8(canny, torch, img, steps, warmup, label):
@@ -223,7 +230,7 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="headline only")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--profile-roofline", action="store_true",
-                    help="only the roofline kernel (float classification pass, 4096^2) and a "
+                    help="only the headline step (float Canny, 4096^2, one buffer set) and a "
                          "256 MiB device copy, for hardware-counter runs")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -239,11 +246,10 @@ def main():
         import numpy as np
         import workloads
         X = torch.from_numpy(workloads.natural_u8(4096, 4096, seed=1).astype(np.float32)).cuda()
+        E = torch.empty((4096, 4096), dtype=torch.uint8, device="cuda")
         ws = torch.empty(canny.f32_workspace_bytes(4096, 4096), dtype=torch.uint8, device="cuda")
-        _, mx = canny.canny_f32(X, with_edges=False, return_max=True, workspace=ws)
-        m = float(mx.cpu()[0])
         for _ in range(args.steps):
-            canny.canny_f32(X, 1.4, 3, 0.05 * m, 0.15 * m, False, with_edges=False, workspace=ws)
+            canny.canny_f32(X, 1.4, 3, 0.05, 0.15, True, edges=E, workspace=ws)
         src = torch.empty(256 << 20, dtype=torch.uint8, device="cuda").fill_(1)
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
@@ -256,7 +262,7 @@ def main():
 
     log("headline: float Canny 4096x4096")
     head, bufs = bench_f32(canny, torch, 4096, 4096, args.steps, args.warmup, seed=1)
-    roof = roofline_f32_pass_b(canny, torch, bufs, 4096, 4096, args.steps, args.warmup)
+    roof = roofline_headline(canny, torch, bufs, 4096, 4096, args.steps)
     del bufs
     torch.cuda.empty_cache()
 

@@ -118,8 +118,11 @@ int canny_hysteresis(const uint8_t* class2, int H, int W, uint8_t* edges, int64_
  *         by the image's largest M before suppression), classes and
  *         hysteresis as in the integer path.
  *
- * in          float H x W, pitch in_pitch floats.
+ * in          float H x W, pitch in_pitch floats; values must be finite.
  * sigma > 0, 1 <= radius <= 8, 0 <= low <= high.
+ * With relative thresholds or max_out, the strength is first stored to the
+ * workspace with its suppression decision and classified by a second,
+ * elementwise pass; otherwise one kernel classifies directly.
  * edges       uint8 output or NULL (class map only).
  * class2      optional class-map output or NULL.
  * mag_out     optional float H x W strength output (pitch W) or NULL.
@@ -188,6 +191,45 @@ size_t canny_mag_backward_workspace_bytes(int N, int H, int W, int radius);
 int canny_mag_backward(const float* I, const float* sigma, const float* dM, int N, int H, int W,
                        int radius, float* dI, float* dsigma, void* ws, size_t ws_bytes,
                        void* stream);
+
+/* ---------------------------------------------------------------------
+ * Stage timing (diagnostics; not part of the paper's operator).
+ *
+ * canny_timing_begin(capacity): 1 <= capacity <= 65536.  Creates
+ *   2 * capacity HIP events per stage on the current device (host-side
+ *   objects, no device memory), discards earlier records, and from then on
+ *   every call that runs a stage records one event before and one after that
+ *   stage's kernels on the call's stream, for the first `capacity` launches
+ *   of each stage.  The interval between the two events includes the
+ *   launch gaps of the stage's kernels.  Do not enable it while a stream is
+ *   being captured into a graph.
+ * canny_timing_read(stage, ms_total, launches): host outputs; waits for the
+ *   recorded events of `stage` and returns the summed milliseconds and the
+ *   number of recorded launches.
+ * canny_timing_end(): stops recording and destroys the events.
+ * Stages: CANNY_STAGE_U8_FORWARD (canny_u8 Steps 1-3 + thresholds),
+ *   CANNY_STAGE_F32_MINMAX (input range pass of canny_f32),
+ *   CANNY_STAGE_F32_WALK (canny_f32 Steps 1-3: the blur/Sobel/suppression
+ *   kernel), CANNY_STAGE_F32_CLASSIFY (canny_f32 thresholds pass),
+ *   CANNY_STAGE_HYSTERESIS (all hysteresis kernels of canny_u8, canny_f32,
+ *   canny_hysteresis), CANNY_STAGE_MAG_FORWARD, CANNY_STAGE_MAG_BACKWARD.
+ * Errors: capacity or stage out of range / NULL outputs ->
+ *   CANNY_ERR_INVALID; event creation or wait failure -> CANNY_ERR_HIP.
+ *   Thread-safe.
+ */
+enum {
+    CANNY_STAGE_U8_FORWARD = 0,
+    CANNY_STAGE_F32_MINMAX = 1,
+    CANNY_STAGE_F32_WALK = 2,
+    CANNY_STAGE_F32_CLASSIFY = 3,
+    CANNY_STAGE_HYSTERESIS = 4,
+    CANNY_STAGE_MAG_FORWARD = 5,
+    CANNY_STAGE_MAG_BACKWARD = 6,
+    CANNY_STAGE_COUNT = 7
+};
+int canny_timing_begin(int capacity);
+int canny_timing_read(int stage, double* ms_total, int64_t* launches);
+int canny_timing_end(void);
 
 #ifdef __cplusplus
 }

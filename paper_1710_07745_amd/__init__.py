@@ -22,7 +22,7 @@ from ._lib import CannyError, check, lib
 __all__ = [
     "canny_u8", "canny_f32", "hysteresis", "class_pitch", "u8_workspace_bytes", "f32_workspace_bytes",
     "BatchPlan", "mag_forward", "mag_backward", "CannyMagnitude", "canny_magnitude",
-    "CannyError",
+    "CannyError", "StageTiming",
 ]
 
 
@@ -254,3 +254,29 @@ class CannyMagnitude(torch.autograd.Function):
 
 def canny_magnitude(I: torch.Tensor, sigma: torch.Tensor, radius: int = 9) -> torch.Tensor:
     return CannyMagnitude.apply(I, sigma, radius)
+
+
+class StageTiming:
+    """Context manager over canny_timing_begin / _read / _end: while open,
+    every library call records HIP events around each stage it runs (first
+    ``capacity`` launches per stage).  ``read(stage)`` returns (total ms,
+    launches) for a stage name of ``STAGES``."""
+
+    STAGES = _lib.STAGES
+
+    def __init__(self, capacity: int = 1024):
+        self.capacity = int(capacity)
+
+    def __enter__(self):
+        check("canny_timing_begin", lib().canny_timing_begin(self.capacity))
+        return self
+
+    def read(self, stage: str):
+        ms = C.c_double(0.0)
+        n = C.c_int64(0)
+        check("canny_timing_read", lib().canny_timing_read(self.STAGES[stage], C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+    def __exit__(self, *exc):
+        lib().canny_timing_end()
+        return False

@@ -44,7 +44,14 @@ SIGNATURES = {
     "canny_mag_forward": (C.c_int, [P, P, C.c_int, C.c_int, C.c_int, C.c_int, P, P]),
     "canny_mag_backward_workspace_bytes": (sz, [C.c_int, C.c_int, C.c_int, C.c_int]),
     "canny_mag_backward": (C.c_int, [P, P, P, C.c_int, C.c_int, C.c_int, C.c_int, P, P, P, sz, P]),
+    "canny_timing_begin": (C.c_int, [C.c_int]),
+    "canny_timing_read": (C.c_int, [C.c_int, C.POINTER(C.c_double), C.POINTER(i64)]),
+    "canny_timing_end": (C.c_int, []),
 }
+
+# stage ids of canny_timing_read (include/canny.h)
+STAGES = {"u8_forward": 0, "f32_minmax": 1, "f32_walk": 2, "f32_classify": 3, "hysteresis": 4,
+          "mag_forward": 5, "mag_backward": 6}
 
 
 class CannyError(RuntimeError):

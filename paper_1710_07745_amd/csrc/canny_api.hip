@@ -12,7 +12,12 @@
 
 namespace canny {
 
-static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+static constexpr size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+static hipError_t timed_hysteresis(const HystArgs& h, int tile_rows, hipStream_t s) {
+    StageTimer t(CANNY_STAGE_HYSTERESIS, s);
+    return launch_hysteresis(h, tile_rows, s);
+}
 
 bool device_ok() {
     static std::mutex mu;
@@ -102,7 +107,11 @@ int canny_u8(const uint8_t* in, int64_t in_pitch, int H, int W, int32_t low, int
     f.high = high > 2040 ? 2040 : high;
     f.cls = class2 ? class2 : reinterpret_cast<uint8_t*>(w);
     f.cpitch = class_pitch(W);
-    hipError_t e = launch_u8_forward(f, 32, s);
+    hipError_t e;
+    {
+        StageTimer t(CANNY_STAGE_U8_FORWARD, s);
+        e = launch_u8_forward(f, 32, s);
+    }
     if (e != hipSuccess || !edges) return status_of(e);
     HystArgs h;
     h.cls = f.cls;
@@ -113,7 +122,7 @@ int canny_u8(const uint8_t* in, int64_t in_pitch, int H, int W, int32_t low, int
     h.epitch = edges_pitch;
     const int T = hyst_tile_rows_default();
     hyst_carve(w + class_bytes(H, W), H, W, T, h);
-    return status_of(launch_hysteresis(h, T, s));
+    return status_of(timed_hysteresis(h, T, s));
 }
 
 size_t canny_hysteresis_workspace_bytes(int H, int W) {
@@ -139,12 +148,17 @@ int canny_hysteresis(const uint8_t* class2, int H, int W, uint8_t* edges, int64_
     h.epitch = edges_pitch;
     const int T = hyst_tile_rows_default();
     hyst_carve(ws, H, W, T, h);
-    return status_of(launch_hysteresis(h, T, static_cast<hipStream_t>(stream)));
+    return status_of(timed_hysteresis(h, T, static_cast<hipStream_t>(stream)));
 }
+
+static int64_t smag_pitch(int W) { return ((int64_t)W + 3) & ~(int64_t)3; }
+// float workspace: largest-strength word, then the min/max partials
+static constexpr size_t kF32Header = 256 + align256(kF32RangeParts * sizeof(float2));
 
 size_t canny_f32_workspace_bytes(int H, int W) {
     if (!size_ok(H, W)) return 0;
-    return 256 + class_bytes(H, W) + hyst_workspace_bytes(H, W, hyst_tile_rows_default());
+    return kF32Header + class_bytes(H, W) + hyst_workspace_bytes(H, W, hyst_tile_rows_default()) +
+           align256((size_t)H * smag_pitch(W) * 4);
 }
 
 int canny_f32(const float* in, int64_t in_pitch, int H, int W, float sigma, int radius, float low,
@@ -183,9 +197,15 @@ int canny_f32(const float* in, int64_t in_pitch, int H, int W, float sigma, int 
     f.low = low;
     f.high = high;
     f.relative = relative ? 1 : 0;
-    f.use_range = (relative || max_out) ? 1 : 0;  // pass A runs and reduces the input range
     f.maxbits = reinterpret_cast<uint32_t*>(w);
-    f.cls = class2 ? class2 : reinterpret_cast<uint8_t*>(w + 256);
+    f.range = reinterpret_cast<float2*>(w + 256);
+    const size_t hyst_off = kF32Header + class_bytes(H, W);
+    if (relative || max_out) {  // the walk stores signed strengths, a second pass classifies
+        f.smag = reinterpret_cast<float*>(w + hyst_off +
+                                          hyst_workspace_bytes(H, W, hyst_tile_rows_default()));
+        f.spitch = smag_pitch(W);
+    }
+    f.cls = class2 ? class2 : reinterpret_cast<uint8_t*>(w + kF32Header);
     f.cpitch = class_pitch(W);
     f.mag = mag_out;
     f.max_out = max_out;
@@ -199,8 +219,8 @@ int canny_f32(const float* in, int64_t in_pitch, int H, int W, float sigma, int 
     h.edges = edges;
     h.epitch = edges_pitch;
     const int T = hyst_tile_rows_default();
-    hyst_carve(w + 256 + class_bytes(H, W), H, W, T, h);
-    return status_of(launch_hysteresis(h, T, s));
+    hyst_carve(w + hyst_off, H, W, T, h);
+    return status_of(timed_hysteresis(h, T, s));
 }
 
 static bool mag_args_ok(const float* I, const float* sigma, int N, int H, int W, int radius) {
@@ -214,6 +234,7 @@ int canny_mag_forward(const float* I, const float* sigma, int N, int H, int W, i
     const size_t n = (size_t)N * H * W * 4;
     if (overlaps(I, n, M, n) || overlaps(sigma, (size_t)N * 4, M, n)) return CANNY_ERR_INVALID;
     if (!device_ok()) return CANNY_ERR_UNSUPPORTED;
+    StageTimer t(CANNY_STAGE_MAG_FORWARD, static_cast<hipStream_t>(stream));
     return status_of(launch_mag_forward(I, sigma, N, H, W, radius, M, static_cast<hipStream_t>(stream)));
 }
 
@@ -234,6 +255,7 @@ int canny_mag_backward(const float* I, const float* sigma, const float* dM, int 
     char* w = static_cast<char*>(ws);
     float* dB = reinterpret_cast<float*>(w);
     float* partial = reinterpret_cast<float*>(w + align256(n));
+    StageTimer t(CANNY_STAGE_MAG_BACKWARD, static_cast<hipStream_t>(stream));
     return status_of(launch_mag_backward(I, sigma, dM, N, H, W, radius, dI, dsigma, dB, partial,
                                          static_cast<hipStream_t>(stream)));
 }

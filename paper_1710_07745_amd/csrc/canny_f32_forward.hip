@@ -13,17 +13,21 @@
 // after they are formed (edge column / edge row copied outward).
 //
 // Relative thresholds need the image's largest strength before any pixel
-// can be classified, so there are two launches: pass A runs the walk up to M
-// and reduces max(Gx^2 + Gy^2) into one word (atomicMax on the float bits,
-// order-independent because the value is non-negative); pass B runs the full
-// walk and derives the thresholds from that word on the device.
+// can be classified.  With absolute thresholds one launch classifies
+// directly.  With relative thresholds (or when the largest strength is
+// requested) the path is: a memory-bound min/max pass over the input, the
+// walk with a threshold-free epilogue that stores the strength with its sign
+// carrying the suppression decision (+M kept, -M suppressed) and reduces the
+// largest M into one word (atomicMax on the float bits, order-independent
+// because the value is non-negative), then an elementwise pass that derives
+// the thresholds from that word and writes the class map.  The walk, the
+// expensive part, therefore runs once per image in both cases.
 //
 // Accuracy: every stage before the strength is linear, and Sobel ignores a
 // constant offset, so the walk filters X - c instead of X, with c the
-// midpoint of the image's value range (min and max are reduced in pass A;
-// without pass A, the midpoint of the wave's first input row).  That halves
-// the magnitude the fp32 accumulations round at, and a constant image gives
-// exactly zero.
+// midpoint of the image's value range (from the min/max pass; without it,
+// the midpoint of the wave's first input row).  That halves the magnitude
+// the fp32 accumulations round at, and a constant image gives exactly zero.
 //
 // Suppression interpolates along the continuous gradient direction: with
 // t = min(|Gx|,|Gy|) / max(|Gx|,|Gy|) and same = (Gx*Gy > 0),
@@ -34,6 +38,7 @@
 // which is the 3x3-ring interpolation where the gradient line leaves the
 // neighbourhood, written with the forward side fixed to the positive step of
 // the dominant axis.
+#include "canny.h"
 #include "canny_internal.h"
 #include "canny_f32_common.h"
 
@@ -56,13 +61,13 @@ __device__ __forceinline__ MRowF selm(bool p, const MRowF& a, const MRowF& b) {
     return r;
 }
 
-template <int R, int RR, bool PASS_B>
+template <int R, int RR, bool SIGNED>
 __global__ void __launch_bounds__(kWGThreads)
 k_f32_forward(F32FwdArgs a, int strips_x, int nwaves, int fast_ok) {
     constexpr int HL = (R + 2 + 3) / 4;  // halo lanes per side
     constexpr int SC = 4 * (kWave - 2 * HL);
     constexpr int HR = R + 2;            // halo rows per side
-    constexpr int NI = PASS_B ? RR + 2 * HR : RR + 2 * HR - 1;
+    constexpr int NI = RR + 2 * HR;
     constexpr int PF = 4;                // rows loaded ahead
 
     const int lane = threadIdx.x & (kWave - 1);
@@ -98,15 +103,7 @@ k_f32_forward(F32FwdArgs a, int strips_x, int nwaves, int fast_ok) {
 #pragma unroll
     for (int j = 0; j <= R; ++j) g[j] = a.g[j];
 
-    float lo = a.low, hi = a.high;
-    if (PASS_B && (a.relative || a.max_out)) {
-        const float mx = sqrtf(bc<float>(*a.maxbits));
-        if (a.relative) {
-            lo = a.low * mx;
-            hi = a.high * mx;
-        }
-        if (a.max_out && wave == 0 && lane == 0) *a.max_out = mx;
-    }
+    const float lo = a.low, hi = a.high;  // absolute thresholds (direct epilogue)
 
     // rolling window: win[0..2R] are input rows vi-2R .. vi, win[2R+1..] are
     // rows loaded PF ahead
@@ -121,8 +118,14 @@ k_f32_forward(F32FwdArgs a, int strips_x, int nwaves, int fast_ok) {
 
     // offset c subtracted from every input value (see the file comment)
     float off;
-    if (PASS_B && a.use_range) {
-        off = 0.5f * ord2f(a.maxbits[1]) + 0.5f * ord2f(a.maxbits[2]);
+    if (SIGNED) {  // image range from the min/max pass's per-workgroup partials
+        float lo = 3.402823466e38f, hi = -3.402823466e38f;
+        for (int j = lane; j < a.nrange; j += kWave) {
+            const float2 p = a.range[j];
+            lo = fminf(lo, p.x);
+            hi = fmaxf(hi, p.y);
+        }
+        off = 0.5f * wave_min(lo) + 0.5f * wave_max(hi);
     } else {
         const F4& r0 = win[2 * R];
         const float lo = wave_min(fminf(fminf(r0.v[0], r0.v[1]), fminf(r0.v[2], r0.v[3])));
@@ -130,22 +133,18 @@ k_f32_forward(F32FwdArgs a, int strips_x, int nwaves, int fast_ok) {
         off = 0.5f * lo + 0.5f * hi;
     }
     off = bc<float>(__builtin_amdgcn_readfirstlane(bc<int>(off)));  // wave-uniform
-    float xmin = 3.402823466e38f, xmax = -3.402823466e38f;  // pass A: input range
 #pragma unroll
     for (int k = 2 * R; k < NW; ++k) {
         if (k - 2 * R < NI) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                if (!PASS_B) { xmin = fminf(xmin, win[k].v[q]); xmax = fmaxf(xmax, win[k].v[q]); }
-                win[k].v[q] -= off;
-            }
+            for (int q = 0; q < 4; ++q) win[k].v[q] -= off;
         }
     }
 
     F4 dxw[3], sxw[3];
     MRowF mw[3];
     F4 gxp, gyp, gxc, gyc;  // gradients of rows g-1 (prev) and g (cur)
-    float smax = 0.0f;
+    float mmax = 0.0f;  // largest M of the rows this wave outputs
 
 #pragma unroll
     for (int i = 0; i < NI; ++i) {
@@ -155,13 +154,7 @@ k_f32_forward(F32FwdArgs a, int strips_x, int nwaves, int fast_ok) {
             if (i + PF < NI) {
                 win[NW - 1] = fetch(i + PF);
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    if (!PASS_B) {
-                        xmin = fminf(xmin, win[NW - 1].v[q]);
-                        xmax = fmaxf(xmax, win[NW - 1].v[q]);
-                    }
-                    win[NW - 1].v[q] -= off;
-                }
+                for (int q = 0; q < 4; ++q) win[NW - 1].v[q] -= off;
             }
         }
         if (i < 2 * R) continue;
@@ -217,14 +210,6 @@ k_f32_forward(F32FwdArgs a, int strips_x, int nwaves, int fast_ok) {
             gy.v[k] = sxw[2].v[k] - sxw[0].v[k];
             s.v[k] = fmaf(gx.v[k], gx.v[k], gy.v[k] * gy.v[k]);
         }
-        if (!PASS_B) {
-            if (gr >= Y0 && gr < Y0 + RR && gr < H && out_lane) {
-#pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    if (!bd.outR[k]) smax = fmaxf(smax, s.v[k]);
-            }
-            continue;
-        }
         gxp = gxc; gyp = gyc;
         gxc = gx; gyc = gy;
         F4 M;
@@ -249,6 +234,7 @@ k_f32_forward(F32FwdArgs a, int strips_x, int nwaves, int fast_ok) {
         const MRowF& c = mw[1];
         const MRowF& d = mw[2];
         uint32_t byte = 0;
+        F4 sv;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const float mc = c.c[k];
@@ -268,39 +254,135 @@ k_f32_forward(F32FwdArgs a, int strips_x, int nwaves, int fast_ok) {
             const float ahead = lerpf_(fp, fd, t);
             const float behind = lerpf_(bp, bdg, t);
             const bool keep = mc > 0.0f && mc > behind && mc >= ahead;
-            const uint32_t code = (keep && mc > hi) ? 2u : ((keep && mc >= lo) ? 1u : 0u);
-            if (!bd.outR[k]) byte |= code << (2 * k);
+            if (SIGNED) {
+                sv.v[k] = keep ? mc : -mc;
+                if (!bd.outR[k]) mmax = fmaxf(mmax, mc);
+            } else {
+                const uint32_t code = (keep && mc > hi) ? 2u : ((keep && mc >= lo) ? 1u : 0u);
+                if (!bd.outR[k]) byte |= code << (2 * k);
+            }
         }
         if (out_lane && c0 < W) {
-            a.cls[(int64_t)n * a.cpitch + (c0 >> 2)] = (uint8_t)byte;
-            if (a.mag) {
-                float* mrow = a.mag + (int64_t)n * W;
+            if (SIGNED) {
+                // row pitch is W rounded up to 4, so the quad store stays inside the row
+                *reinterpret_cast<float4*>(a.smag + (int64_t)n * a.spitch + c0) =
+                    make_float4(sv.v[0], sv.v[1], sv.v[2], sv.v[3]);
+            } else {
+                a.cls[(int64_t)n * a.cpitch + (c0 >> 2)] = (uint8_t)byte;
+                if (a.mag) {
+                    float* mrow = a.mag + (int64_t)n * W;
 #pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    if (!bd.outR[k]) mrow[c0 + k] = c.c[k];
+                    for (int k = 0; k < 4; ++k)
+                        if (!bd.outR[k]) mrow[c0 + k] = c.c[k];
+                }
             }
         }
     }
 
-    if (!PASS_B) {
-        uint32_t v = bc<uint32_t>(smax);
+    if (SIGNED) {
+        const float wmax = out_lane ? mmax : 0.0f;
+        const uint32_t v = bc<uint32_t>(wave_max(wmax));
+        if (lane == 0 && v) atomicMax(a.maxbits, v);
+    }
+}
+
+constexpr int kRowThreads = 256;  // one workgroup walks whole rows
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Input min and max, one (min, max) pair per workgroup written to
+// a.range[blockIdx.x] (no atomics: the walk reduces the pairs itself).
+// Workgroup b takes rows b, b + gridDim.x, ...; each thread takes float4
+// quads of a row.  Also clears the largest-strength word the walk reduces
+// into, which is safe because the walk is launched after this kernel.
+__global__ void __launch_bounds__(kRowThreads)
+k_f32_minmax(F32FwdArgs a, int quads_ok) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *a.maxbits = 0u;
+    float lo = 3.402823466e38f, hi = -3.402823466e38f;
+    const int W = a.W;
+    const int nq = W >> 2;
+    for (int y = blockIdx.x; y < a.H; y += gridDim.x) {
+        const float* row = a.in + (int64_t)y * a.pitch;
+        int x0 = 0;
+        if (quads_ok) {
+            const f32x4* r4 = reinterpret_cast<const f32x4*>(row);
+            for (int q = threadIdx.x; q < nq; q += kRowThreads) {
+                const f32x4 v = r4[q];
+                lo = fminf(lo, fminf(fminf(v.x, v.y), fminf(v.z, v.w)));
+                hi = fmaxf(hi, fmaxf(fmaxf(v.x, v.y), fmaxf(v.z, v.w)));
+            }
+            x0 = 4 * nq;
+        }
+        for (int x = x0 + threadIdx.x; x < W; x += kRowThreads) {
+            lo = fminf(lo, row[x]);
+            hi = fmaxf(hi, row[x]);
+        }
+    }
+    __shared__ float2 part[kRowThreads / kWave];
+    lo = wave_min(lo);
+    hi = wave_max(hi);
+    const int wv = threadIdx.x / kWave;
+    if ((threadIdx.x & (kWave - 1)) == 0) part[wv] = make_float2(lo, hi);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float2 r = part[0];
+        for (int k = 1; k < kRowThreads / kWave; ++k) {
+            r.x = fminf(r.x, part[k].x);
+            r.y = fmaxf(r.y, part[k].y);
+        }
+        a.range[blockIdx.x] = r;
+    }
+}
+
+// Thresholds and classes from the signed strength map: a pixel is kept iff
+// its stored value is positive (M > 0 and not suppressed); then strong iff
+// M > high, weak iff M >= low, with low/high scaled by the largest M when
+// thresholds are relative.  Each thread packs 16 pixels into one 32-bit
+// word of the class map.
+__global__ void __launch_bounds__(kRowThreads)
+k_f32_classify(F32FwdArgs a) {
+    const float mx = bc<float>(a.maxbits[0]);
+    const float lo = a.relative ? a.low * mx : a.low;
+    const float hi = a.relative ? a.high * mx : a.high;
+    if (a.max_out && blockIdx.x == 0 && threadIdx.x == 0) *a.max_out = mx;
+    const int W = a.W;
+    const int nq = (W + 3) >> 2;     // quads of the row (pitch holds them all)
+    const int nw = (nq + 3) >> 2;    // 16-pixel words
+    const bool mag4 = a.mag && (W % 4 == 0) && ((uintptr_t)a.mag % 16 == 0);
+    for (int y = blockIdx.x; y < a.H; y += gridDim.x) {
+        const float* srow = a.smag + (int64_t)y * a.spitch;
+        uint32_t* crow = reinterpret_cast<uint32_t*>(a.cls + (int64_t)y * a.cpitch);
+        for (int w = threadIdx.x; w < nw; w += kRowThreads) {
+            uint32_t word = 0;
 #pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o));
-        const float wmin = wave_min(xmin), wmax = wave_max(xmax);
-        if (lane == 0) {
-            if (v) atomicMax(a.maxbits, v);
-            atomicMin(a.maxbits + 1, f2ord(wmin));
-            atomicMax(a.maxbits + 2, f2ord(wmax));
+            for (int j = 0; j < 4; ++j) {
+                const int q = 4 * w + j;
+                if (q >= nq) break;
+                const f32x4 v4 = reinterpret_cast<const f32x4*>(srow)[q];
+                const float v[4] = {v4.x, v4.y, v4.z, v4.w};
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int x = 4 * q + k;
+                    const uint32_t code = (x < W && v[k] > 0.0f) ? (v[k] > hi ? 2u : (v[k] >= lo ? 1u : 0u)) : 0u;
+                    word |= code << (8 * j + 2 * k);
+                }
+                if (a.mag) {
+                    float* mrow = a.mag + (int64_t)y * W;
+                    if (mag4) {
+                        *reinterpret_cast<float4*>(mrow + 4 * q) =
+                            make_float4(fabsf(v[0]), fabsf(v[1]), fabsf(v[2]), fabsf(v[3]));
+                    } else {
+#pragma unroll
+                        for (int k = 0; k < 4; ++k)
+                            if (4 * q + k < W) mrow[4 * q + k] = fabsf(v[k]);
+                    }
+                }
+            }
+            crow[w] = word;
         }
     }
 }
 
-// resets the max-pass words: max M^2 = 0, min code = all ones, max code = 0
-__global__ void k_reset_range(uint32_t* p) {
-    p[0] = 0u;
-    p[1] = 0xFFFFFFFFu;
-    p[2] = 0u;
-}
+int rows_grid(int H) { return min(H, 8 * 256); }
 
 template <int R>
 hipError_t launch_radius(const F32FwdArgs& a, hipStream_t s) {
@@ -311,13 +393,27 @@ hipError_t launch_radius(const F32FwdArgs& a, hipStream_t s) {
     const int nwaves = strips_x * ceil_div(a.H, RR);
     const int nwg = ceil_div(nwaves, kWavesPerWG);
     const int fast_ok = ((uintptr_t)a.in % 16 == 0) && (a.pitch % 4 == 0);
-    if (a.relative || a.max_out) {
-        hipLaunchKernelGGL(k_reset_range, dim3(1), dim3(1), 0, s, a.maxbits);
+    if (!a.smag) {  // absolute thresholds, no max: classify in the walk
+        StageTimer t(CANNY_STAGE_F32_WALK, s);
         hipLaunchKernelGGL((k_f32_forward<R, RR, false>), dim3(nwg), dim3(kWGThreads), 0, s, a,
                            strips_x, nwaves, fast_ok);
+        return hipGetLastError();
     }
-    hipLaunchKernelGGL((k_f32_forward<R, RR, true>), dim3(nwg), dim3(kWGThreads), 0, s, a,
-                       strips_x, nwaves, fast_ok);
+    F32FwdArgs b = a;
+    b.nrange = min(a.H, kF32RangeParts);
+    {
+        StageTimer t(CANNY_STAGE_F32_MINMAX, s);
+        hipLaunchKernelGGL(k_f32_minmax, dim3(b.nrange), dim3(kRowThreads), 0, s, b, fast_ok);
+    }
+    {
+        StageTimer t(CANNY_STAGE_F32_WALK, s);
+        hipLaunchKernelGGL((k_f32_forward<R, RR, true>), dim3(nwg), dim3(kWGThreads), 0, s, b,
+                           strips_x, nwaves, fast_ok);
+    }
+    {
+        StageTimer t(CANNY_STAGE_F32_CLASSIFY, s);
+        hipLaunchKernelGGL(k_f32_classify, dim3(rows_grid(a.H)), dim3(kRowThreads), 0, s, b);
+    }
     return hipGetLastError();
 }
 

@@ -101,14 +101,30 @@ struct F32FwdArgs {
     int radius;
     float low, high;
     int relative;
-    uint32_t* maxbits;  // device words: [0] float bits of max M^2 (>= 0),
-                        // [1] / [2] order-preserving codes of min / max input value
-    int use_range;      // pass B subtracts the midpoint of words [1], [2]
+    uint32_t* maxbits;  // device word: float bits of the largest M (>= 0)
+    float2* range;      // per-workgroup (min, max) of the input, nrange entries
+    int nrange;
+    float* smag;        // signed strength map (+M kept, -M suppressed) or NULL for
+    int64_t spitch;     // the one-launch absolute path; pitch in floats, multiple of 4
     uint8_t* cls;
     int64_t cpitch;
     float* mag;       // optional
     float* max_out;   // optional
 };
+// stage timing (canny_timing.hip): timing_begin returns a slot (or -1 when
+// timing is off or the stage's pool is full) that timing_end closes
+int timing_begin(int stage, hipStream_t s);
+void timing_end(int stage, int slot, hipStream_t s);
+struct StageTimer {
+    int stage, slot;
+    hipStream_t s;
+    StageTimer(int st, hipStream_t st_s) : stage(st), slot(timing_begin(st, st_s)), s(st_s) {}
+    ~StageTimer() { timing_end(stage, slot, s); }
+    StageTimer(const StageTimer&) = delete;
+    StageTimer& operator=(const StageTimer&) = delete;
+};
+
+constexpr int kF32RangeParts = 512;  // workgroups of the input min/max pass
 hipError_t launch_f32_forward(const F32FwdArgs& a, hipStream_t s);
 
 // ---------------------------------------------------------------- batches

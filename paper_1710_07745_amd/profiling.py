@@ -1,0 +1,141 @@
+"""Summaries of rocprofv3 output for the measurements kept under profiles/.
+
+  python -m paper_1710_07745_amd.profiling stats DIR [--title T] [--command C]
+      kernel table from DIR/*_kernel_stats.csv (rocprofv3 --kernel-trace
+      --stats --output-format csv).
+  python -m paper_1710_07745_amd.profiling traffic FETCH_DIR WRITE_DIR
+      --kernel SUBSTR --copy-bytes N [--command C ...]
+      HBM bytes per launch of the kernel whose name contains SUBSTR, from two
+      counter runs (FETCH_SIZE, then WRITE_SIZE, each in KiB per dispatch; the median over dispatches).
+      Each counter is scaled by what it reads for the device copy kernel of
+      N bytes in the same run (a copy fetches N and writes N bytes).
+
+The float walk's traffic line carries a hash of the kernel's sources; the
+benchmark reports that traffic only while the hash still matches.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+WALK_SOURCES = ("paper_1710_07745_amd/csrc/canny_f32_forward.hip",
+                "paper_1710_07745_amd/csrc/canny_f32_common.h",
+                "paper_1710_07745_amd/csrc/canny_internal.h")
+WALK_KERNEL = "k_f32_forward<3, 32, true>"
+COPY_KERNEL = "copy"  # the device-to-device copy kernel's name contains this
+
+
+def walk_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in WALK_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def read_traffic(path: str):
+    """traffic_bytes_per_launch from a traffic summary, or None when the
+    file is missing or the walk's sources changed since it was taken."""
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for ln in open(path):
+        if ":" in ln and not ln.lstrip().startswith("#"):
+            k, v = ln.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_sha256") != walk_source_hash():
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def _one(pattern: str) -> str:
+    files = sorted(glob.glob(pattern))
+    if not files:
+        sys.exit(f"no file matches {pattern}")
+    return files[0]
+
+
+def short(name: str, n: int = 90) -> str:
+    name = name.replace("canny::(anonymous namespace)::", "").replace("void ", "")
+    return name if len(name) <= n else name[: n - 3] + "..."
+
+
+def stats(args) -> None:
+    rows = list(csv.DictReader(open(_one(os.path.join(args.dir, "*kernel_stats.csv")))))
+    print(f"# {args.title}")
+    if args.command:
+        print(f"# command: {args.command}")
+    print(f"{'calls':>6} {'avg_us':>9} {'min_us':>9} {'max_us':>9} {'share%':>7}  kernel")
+    for r in rows:
+        print(f"{int(r['Calls']):6d} {float(r['AverageNs']) / 1e3:9.2f} {float(r['MinNs']) / 1e3:9.2f} "
+              f"{float(r['MaxNs']) / 1e3:9.2f} {float(r['Percentage']):7.2f}  {short(r['Name'])}")
+
+
+def _per_dispatch(d: str, counter: str, substr: str):
+    vals = []
+    for r in csv.DictReader(open(_one(os.path.join(d, "*counter_collection.csv")))):
+        if r["Counter_Name"] == counter and substr in r["Kernel_Name"]:
+            vals.append(float(r["Counter_Value"]))
+    if not vals:
+        sys.exit(f"no {counter} rows for kernels matching {substr!r} in {d}")
+    vals.sort()
+    return vals[len(vals) // 2], len(vals)  # median: ignores a stray upload copy
+
+
+def traffic(args) -> None:
+    kib = 1024.0
+    f_k, nf = _per_dispatch(args.fetch_dir, "FETCH_SIZE", args.kernel)
+    w_k, nw = _per_dispatch(args.write_dir, "WRITE_SIZE", args.kernel)
+    f_c, _ = _per_dispatch(args.fetch_dir, "FETCH_SIZE", COPY_KERNEL)
+    w_c, _ = _per_dispatch(args.write_dir, "WRITE_SIZE", COPY_KERNEL)
+    fs = args.copy_bytes / (f_c * kib)
+    ws = args.copy_bytes / (w_c * kib)
+    total = f_k * kib * fs + w_k * kib * ws
+    print(f"# HBM traffic of {args.kernel} (hardware counters, per dispatch)")
+    for c in args.command or []:
+        print(f"# command: {c}")
+    print(f"kernel: {args.kernel}")
+    print(f"source_sha256: {walk_source_hash()}")
+    print(f"dispatches_fetch: {nf}")
+    print(f"dispatches_write: {nw}")
+    print(f"fetch_kib_per_dispatch: {f_k:.1f}")
+    print(f"write_kib_per_dispatch: {w_k:.1f}")
+    print(f"copy_bytes: {args.copy_bytes}")
+    print(f"copy_fetch_kib: {f_c:.1f}")
+    print(f"copy_write_kib: {w_c:.1f}")
+    print(f"fetch_scale: {fs:.4f}")
+    print(f"write_scale: {ws:.4f}")
+    print(f"traffic_bytes_per_launch: {total:.0f}")
+    if args.alg_bytes:
+        print(f"algorithmic_bytes_per_launch: {args.alg_bytes:.0f}")
+        print(f"traffic_over_algorithmic: {total / args.alg_bytes:.3f}")
+
+
+def main(argv=None) -> None:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("dir")
+    s.add_argument("--title", default="rocprofv3 kernel statistics")
+    s.add_argument("--command", default="")
+    t = sub.add_parser("traffic")
+    t.add_argument("fetch_dir")
+    t.add_argument("write_dir")
+    t.add_argument("--kernel", default=WALK_KERNEL)
+    t.add_argument("--copy-bytes", type=float, required=True)
+    t.add_argument("--alg-bytes", type=float, default=0.0)
+    t.add_argument("--command", action="append")
+    a = ap.parse_args(argv)
+    stats(a) if a.cmd == "stats" else traffic(a)
+
+
+if __name__ == "__main__":
+    main()

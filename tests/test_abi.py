@@ -99,3 +99,17 @@ def test_host_validation_mag_and_batch(lib):
     assert lib.canny_batch(None, None, None, None, None, None, 0, None) == 1
     assert lib.canny_batch_workspace_bytes(None) == 0
     lib.canny_batch_plan_destroy(None)
+
+
+def test_timing_validation(lib):
+    """Argument checks of the stage-timing calls (no events are created)."""
+    ms = C.c_double(-1.0)
+    n = C.c_int64(-1)
+    assert lib.canny_timing_begin(0) == 1
+    assert lib.canny_timing_begin(65537) == 1
+    assert lib.canny_timing_read(7, C.byref(ms), C.byref(n)) == 1
+    assert lib.canny_timing_read(-1, C.byref(ms), C.byref(n)) == 1
+    assert lib.canny_timing_read(2, None, C.byref(n)) == 1
+    assert lib.canny_timing_read(2, C.byref(ms), C.byref(n)) == 0  # nothing recorded
+    assert ms.value == 0.0 and n.value == 0
+    assert lib.canny_timing_end() == 0

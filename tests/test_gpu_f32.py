@@ -26,24 +26,29 @@ def canny():
     return m
 
 
-def run_f32(canny, X, **kw):
+def run_f32(canny, X, with_max=True, **kw):
+    """Requesting the largest strength (or relative thresholds) selects the
+    signed-strength path; absolute thresholds without it select the one-launch
+    path that classifies inside the walk."""
     H, W = X.shape
     dev = torch.from_numpy(np.ascontiguousarray(X, dtype=np.float32)).cuda()
-    e, cls, mag, mx = canny.canny_f32(dev, return_classes=True, return_magnitude=True,
-                                      return_max=True, **kw)
+    out = canny.canny_f32(dev, return_classes=True, return_magnitude=True, return_max=with_max,
+                          **kw)
+    e, cls, mag = out[:3]
+    mx = float(out[3].cpu()[0]) if with_max else None
     torch.cuda.synchronize()
-    return (e.cpu().numpy(), unpack_classes(cls.cpu().numpy(), H, W), mag.cpu().numpy(),
-            float(mx.cpu()[0]))
+    return e.cpu().numpy(), unpack_classes(cls.cpu().numpy(), H, W), mag.cpu().numpy(), mx
 
 
 def check_float(canny, X, sigma=1.4, R=3, low=0.05, high=0.15, relative=True, max_unamb_diff=0,
-                tol=TOL):
-    e, c, m, mx = run_f32(canny, X, sigma=sigma, radius=R, low=low, high=high, relative=relative)
+                tol=TOL, with_max=True):
+    e, c, m, mx = run_f32(canny, X, with_max=with_max, sigma=sigma, radius=R, low=low, high=high,
+                          relative=relative)
     oc, oM, amb, omx = oracle.classify_f32(X, sigma, R, low, high, relative, tol)
     floor = 0.05 * omx
     err = np.abs(m - oM) / np.maximum(np.maximum(oM, floor), 1e-30)
     assert err.max() <= tol or omx == 0.0, f"strength error {err.max():.3g}"
-    if relative:
+    if with_max:
         assert abs(mx - omx) <= tol * omx
     unamb = (amb & 3) == 0
     diff = (c != oc) & unamb
@@ -80,9 +85,53 @@ def test_float_small_sizes(canny, H):
         check_float(canny, X)
 
 
-def test_float_absolute_thresholds(canny):
+@pytest.mark.parametrize("with_max", [True, False])
+def test_float_absolute_thresholds(canny, with_max):
     X = workloads.natural_u8(200, 333, seed=3).astype(np.float32)
-    check_float(canny, X, low=20.0, high=60.0, relative=False)
+    check_float(canny, X, low=20.0, high=60.0, relative=False, with_max=with_max)
+
+
+def absolute_like_relative(X, sigma=1.4, R=3):
+    """Absolute thresholds equal to 0.05 / 0.15 of the oracle's largest strength."""
+    _, _, _, omx = oracle.classify_f32(X, sigma, R)
+    return 0.05 * omx, 0.15 * omx
+
+
+@pytest.mark.parametrize("H", [1, 2, 5, 13, 33, 40])
+def test_float_one_launch_small_sizes(canny, H):
+    for W in [1, 3, 4, 5, 17, 40, 247, 248, 249]:
+        X = workloads.natural_u8(H, W, seed=300 + H * 64 + W).astype(np.float32)
+        lo, hi = absolute_like_relative(X)
+        check_float(canny, X, low=lo, high=hi, relative=False, with_max=False)
+
+
+def test_float_one_launch_ragged(canny):
+    X = workloads.natural_u8(1001, 2049, seed=13).astype(np.float32)
+    lo, hi = absolute_like_relative(X)
+    check_float(canny, X, low=lo, high=hi, relative=False, with_max=False)
+
+
+def test_float_one_launch_4096(canny):
+    """The launch the bench times for the classification walk alone."""
+    X = workloads.natural_u8(4096, 4096, seed=1).astype(np.float32)
+    lo, hi = absolute_like_relative(X)
+    check_float(canny, X, low=lo, high=hi, relative=False, with_max=False)
+
+
+def test_float_unaligned_pitch(canny):
+    """Row pitch not a multiple of 4 floats: scalar loads in every pass."""
+    X = workloads.natural_u8(77, 301, seed=21).astype(np.float32)
+    H, W = X.shape
+    big = torch.zeros((H, W + 3), dtype=torch.float32, device="cuda")
+    big[:, 1:W + 1] = torch.from_numpy(X).cuda()
+    view = big[:, 1:W + 1]
+    for rel, lo, hi in [(True, 0.05, 0.15), (False,) + absolute_like_relative(X)]:
+        e, cls = canny.canny_f32(view, 1.4, 3, lo, hi, rel, return_classes=True)
+        c = unpack_classes(cls.cpu().numpy(), H, W)
+        oc, _, amb, _ = oracle.classify_f32(X, 1.4, 3, lo, hi, rel, TOL)
+        assert ((c != oc) & ((amb & 3) == 0)).sum() == 0
+        be, _ = oracle.hysteresis(c)
+        assert np.array_equal(e.cpu().numpy(), be)
 
 
 def test_float_constant(canny):
@@ -103,3 +152,20 @@ def test_float_4096(canny):
 def test_float_7680x4320(canny):
     X = workloads.natural_u8(4320, 7680, seed=2).astype(np.float32)
     check_float(canny, X)
+
+
+def test_float_stage_timing(canny):
+    """Stage timing records one event pair per stage and call and leaves the
+    results unchanged."""
+    X = workloads.natural_u8(300, 500, seed=31).astype(np.float32)
+    dev = torch.from_numpy(X).cuda()
+    ref_e, ref_c = canny.canny_f32(dev, return_classes=True)
+    with canny.StageTiming(8) as t:
+        for _ in range(3):
+            e, c = canny.canny_f32(dev, return_classes=True)
+        torch.cuda.synchronize()
+        for stage in ("f32_minmax", "f32_walk", "f32_classify", "hysteresis"):
+            ms, n = t.read(stage)
+            assert n == 3 and ms > 0.0, stage
+        assert t.read("u8_forward") == (0.0, 0)
+    assert torch.equal(e, ref_e) and torch.equal(c, ref_c)
