@@ -71,10 +71,11 @@ __device__ __forceinline__ void fix_cols(F4& x, const BorderF& bd) {
         for (int k = 0; k < 4; ++k) x.v[k] = bd.outL[k] ? v : x.v[k];
     }
     if (bd.right) {
-        float src = x.v[0];
-        if (bd.lw_px == 1) src = x.v[1];
-        if (bd.lw_px == 2) src = x.v[2];
-        if (bd.lw_px == 3) src = x.v[3];
+        // explicit selects on the wave-uniform lw_px: a dynamic index into x
+        // would make the compiler stage the row through LDS
+        const float src = bd.lw_px == 0 ? x.v[0]
+                        : bd.lw_px == 1 ? x.v[1]
+                        : bd.lw_px == 2 ? x.v[2] : x.v[3];
         const float v = bc<float>(__builtin_amdgcn_readlane(bc<int>(src), bd.lw_lane));
 #pragma unroll
         for (int k = 0; k < 4; ++k) x.v[k] = bd.outR[k] ? v : x.v[k];

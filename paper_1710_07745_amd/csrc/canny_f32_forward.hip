@@ -38,7 +38,7 @@
 // which is the 3x3-ring interpolation where the gradient line leaves the
 // neighbourhood, written with the forward side fixed to the positive step of
 // the dominant axis.
-#include "canny.h"
+#include "../../include/canny.h"
 #include "canny_internal.h"
 #include "canny_f32_common.h"
 
@@ -50,8 +50,6 @@ struct MRowF {
     float l, r;  // column c0-1 and c0+4
 };
 
-__device__ __forceinline__ float lerpf_(float p, float d, float t) { return fmaf(t, d - p, p); }
-
 __device__ __forceinline__ MRowF selm(bool p, const MRowF& a, const MRowF& b) {
     MRowF r;
 #pragma unroll
@@ -61,30 +59,47 @@ __device__ __forceinline__ MRowF selm(bool p, const MRowF& a, const MRowF& b) {
     return r;
 }
 
-template <int R, int RR, bool SIGNED>
-__global__ void __launch_bounds__(kWGThreads)
-k_f32_forward(F32FwdArgs a, int strips_x, int nwaves, int fast_ok) {
-    constexpr int HL = (R + 2 + 3) / 4;  // halo lanes per side
-    constexpr int SC = 4 * (kWave - 2 * HL);
-    constexpr int HR = R + 2;            // halo rows per side
-    constexpr int NI = RR + 2 * HR;
-    constexpr int PF = 4;                // rows loaded ahead
+template <int R>
+struct WalkShape {
+    static constexpr int HL = (R + 2 + 3) / 4;        // halo lanes per side
+    static constexpr int SC = 4 * (kWave - 2 * HL);   // output columns per wave
+    static constexpr int HR = R + 2;                  // halo rows per side
+};
 
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wave_in_wg = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int wg = xcd_remap(blockIdx.x, gridDim.x);
-    const int wave = wg * kWavesPerWG + wave_in_wg;
-    if (wave >= nwaves) return;
-    const int strip = wave % strips_x;
-    const int blk = wave / strips_x;
-    const int X0 = strip * SC;
-    const int Y0 = blk * RR;
+// One wave's strip: output rows Y0 .. Y0 + RR - 1, columns X0 .. X0 + SC - 1.
+//
+// The row loop is unrolled completely (every row index is a compile-time
+// constant, so the per-row arrays below live in registers and sliding
+// windows are plain renaming) and software-pipelined: iteration i blurs row
+// i - R, forms the Sobel row terms of row i - R - 1, the gradients and
+// strength of row i - R - 3 and the suppression of row i - R - 5 (row
+// numbers relative to the first input row Y0 - HR).  Each stage reads only
+// what earlier iterations produced, so the four stages of one iteration are
+// independent instruction streams the scheduler can interleave, instead of
+// one long dependency chain per row.
+//
+// EDGE = false is the interior case (every lane and every row inside the
+// image, rows 16-byte aligned): no clamps and no replicate fix-ups.  EDGE =
+// true handles strips and rows that touch the image border: clamped loads,
+// edge columns copied outward, and the rows above row 0 / below row H-1
+// replaced by the edge row where a stage reads them.
+template <int R, int RR, bool SIGNED, bool EDGE>
+__device__ __forceinline__ void f32_walk(const F32FwdArgs& a, int X0, int Y0, int lane, int fast_ok) {
+    constexpr int HL = WalkShape<R>::HL;
+    constexpr int HR = WalkShape<R>::HR;
+    constexpr int NI = RR + 2 * HR;          // input rows
+    constexpr int PF = 4;                    // rows loaded ahead of use
+    constexpr int TB0 = R, TB1 = RR + R + 3;      // rows blurred / Sobel terms
+    constexpr int TG0 = R + 1, TG1 = RR + R + 2;  // rows with gradients and strength
+    constexpr int TN0 = R + 2, TN1 = RR + R + 1;  // output rows
+    constexpr int NIT = TN1 + R + 5 + 1;          // iterations (last: suppression of TN1)
     const int H = a.H, W = a.W;
     const int c0 = X0 - 4 * HL + 4 * lane;
+    const int ybase = Y0 - HR;  // absolute row of relative row 0
 
     BorderF bd;
     bd.left = X0 == 0;
-    bd.right = X0 + SC + 4 * HL > W;
+    bd.right = X0 + WalkShape<R>::SC + 4 * HL > W;
     bd.l0_lane = HL;
     {
         const int off = W - 1 - (X0 - 4 * HL);
@@ -97,224 +112,286 @@ k_f32_forward(F32FwdArgs a, int strips_x, int nwaves, int fast_ok) {
         bd.outR[k] = c0 + k >= W;
     }
     const bool out_lane = lane >= HL && lane < kWave - HL;
-    const bool fast = fast_ok && c0 >= 0 && c0 + 4 <= W;
 
     float g[R + 1];
 #pragma unroll
     for (int j = 0; j <= R; ++j) g[j] = a.g[j];
 
-    const float lo = a.low, hi = a.high;  // absolute thresholds (direct epilogue)
-
-    // rolling window: win[0..2R] are input rows vi-2R .. vi, win[2R+1..] are
-    // rows loaded PF ahead
-    constexpr int NW = 2 * R + 1 + PF;
-    auto fetch = [&](int i) -> F4 {
-        const int y = min(max(Y0 - HR + i, 0), H - 1);
-        return load_row(a.in + (int64_t)y * a.pitch, c0, W, fast);
-    };
-    F4 win[NW];
+    // edge strips read every pixel with a clamped column index (4 loads per
+    // row, no divergence); interior strips read one float4 per lane
+    int cx[4];
 #pragma unroll
-    for (int k = 0; k < NW; ++k) win[k] = (k >= 2 * R && k - 2 * R < NI) ? fetch(k - 2 * R) : F4{};
+    for (int k = 0; k < 4; ++k) cx[k] = min(max(c0 + k, 0), W - 1);
+    auto fetch = [&](int t) -> F4 {
+        F4 r;
+        if (EDGE) {
+            const int y = min(max(ybase + t, 0), H - 1);
+            const float* row = a.in + (int64_t)y * a.pitch;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) r.v[k] = row[cx[k]];
+        } else {
+            const float4 q = *reinterpret_cast<const float4*>(a.in + (int64_t)(ybase + t) * a.pitch + c0);
+            r.v[0] = q.x; r.v[1] = q.y; r.v[2] = q.z; r.v[3] = q.w;
+        }
+        return r;
+    };
+    F4 in[NI];
+#pragma unroll
+    for (int k = 0; k < PF && k < NI; ++k) in[k] = fetch(k);
 
     // offset c subtracted from every input value (see the file comment)
     float off;
     if (SIGNED) {  // image range from the min/max pass's per-workgroup partials
         float lo = 3.402823466e38f, hi = -3.402823466e38f;
-        for (int j = lane; j < a.nrange; j += kWave) {
-            const float2 p = a.range[j];
-            lo = fminf(lo, p.x);
-            hi = fmaxf(hi, p.y);
+#pragma unroll
+        for (int u = 0; u < kF32RangeParts / kWave; ++u) {  // all loads in flight at once
+            const int j = lane + u * kWave;
+            if (j < a.nrange) {
+                const float2 p = a.range[j];
+                lo = fminf(lo, p.x);
+                hi = fmaxf(hi, p.y);
+            }
         }
         off = 0.5f * wave_min(lo) + 0.5f * wave_max(hi);
     } else {
-        const F4& r0 = win[2 * R];
+        const F4& r0 = in[0];
         const float lo = wave_min(fminf(fminf(r0.v[0], r0.v[1]), fminf(r0.v[2], r0.v[3])));
         const float hi = wave_max(fmaxf(fmaxf(r0.v[0], r0.v[1]), fmaxf(r0.v[2], r0.v[3])));
         off = 0.5f * lo + 0.5f * hi;
     }
     off = bc<float>(__builtin_amdgcn_readfirstlane(bc<int>(off)));  // wave-uniform
-#pragma unroll
-    for (int k = 2 * R; k < NW; ++k) {
-        if (k - 2 * R < NI) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) win[k].v[q] -= off;
-        }
-    }
 
-    F4 dxw[3], sxw[3];
-    MRowF mw[3];
-    F4 gxp, gyp, gxc, gyc;  // gradients of rows g-1 (prev) and g (cur)
+    // per-row values, indexed by relative row (compile-time indices only)
+    F4 Bv[NI], dxv[NI], sxv[NI], gxv[NI], gyv[NI];
+    MRowF mv[NI];
     float mmax = 0.0f;  // largest M of the rows this wave outputs
 
 #pragma unroll
-    for (int i = 0; i < NI; ++i) {
-        if (i > 0) {
+    for (int i = 0; i < NIT; ++i) {
+        if (i + PF < NI) in[i + PF] = fetch(i + PF);
+        if (i < NI) {
 #pragma unroll
-            for (int k = 0; k < NW - 1; ++k) win[k] = win[k + 1];
-            if (i + PF < NI) {
-                win[NW - 1] = fetch(i + PF);
-#pragma unroll
-                for (int q = 0; q < 4; ++q) win[NW - 1].v[q] -= off;
-            }
+            for (int q = 0; q < 4; ++q) in[i].v[q] -= off;
         }
-        if (i < 2 * R) continue;
-        // ---- Step 1: Gaussian, row b = vi - R (vertical taps, then horizontal)
-        const int b = Y0 - HR + i - R;
-        F4 V;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            float acc = g[0] * win[R].v[k];
-#pragma unroll
-            for (int j = 1; j <= R; ++j) acc = fmaf(g[j], win[R - j].v[k] + win[R + j].v[k], acc);
-            V.v[k] = acc;
-        }
-        float ext[4 + 2 * R];
-#pragma unroll
-        for (int e = -R; e < 4 + R; ++e) ext[e + R] = lane_ext(V, e);
-        F4 B;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            float acc = g[0] * ext[k + R];
-#pragma unroll
-            for (int j = 1; j <= R; ++j) acc = fmaf(g[j], ext[k + R - j] + ext[k + R + j], acc);
-            B.v[k] = acc;
-        }
-        fix_cols(B, bd);
-        // ---- Step 2a: Sobel row terms
-        const float bl = from_left_f(B.v[3]), br = from_right_f(B.v[0]);
-        F4 dx, sx;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const float xm = k == 0 ? bl : B.v[k - 1];
-            const float xp = k == 3 ? br : B.v[k + 1];
-            dx.v[k] = xp - xm;
-            sx.v[k] = fmaf(2.0f, B.v[k], xm + xp);
-        }
-        dxw[0] = dxw[1]; dxw[1] = dxw[2];
-        sxw[0] = sxw[1]; sxw[1] = sxw[2];
-        const bool below = b >= H, top = b == 0;  // rows outside replicate the edge row
-        dxw[2] = sel4(below, dxw[1], dx);
-        sxw[2] = sel4(below, sxw[1], sx);
-        dxw[1] = sel4(top, dx, dxw[1]);
-        sxw[1] = sel4(top, sx, sxw[1]);
-        dxw[0] = sel4(top, dx, dxw[0]);
-        sxw[0] = sel4(top, sx, sxw[0]);
-        if (i < 2 * R + 2) continue;
 
-        // ---- Step 2b: gradients and strength of row gr = b - 1
-        const int gr = b - 1;
-        F4 gx, gy, s;
+        // ---- Step 3 + thresholds: suppression of row tD
+        const int tD = i - R - 5;
+        if (tD >= TN0 && tD <= TN1) {
+            const int n = ybase + tD;
+            if (!EDGE || n < H) {
+                const MRowF& c = mv[tD];
+                MRowF u = mv[tD - 1], d = mv[tD + 1];
+                if (EDGE) {  // rows -1 and H replicate rows 0 and H-1
+                    u = selm(n == 0, c, u);
+                    d = selm(n == H - 1, c, d);
+                }
+                uint32_t byte = 0;
+                F4 sv;
+                float rmax = 0.0f;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            gx.v[k] = fmaf(2.0f, dxw[1].v[k], dxw[0].v[k] + dxw[2].v[k]);
-            gy.v[k] = sxw[2].v[k] - sxw[0].v[k];
-            s.v[k] = fmaf(gx.v[k], gx.v[k], gy.v[k] * gy.v[k]);
-        }
-        gxp = gxc; gyp = gyc;
-        gxc = gx; gyc = gy;
-        F4 M;
+                for (int k = 0; k < 4; ++k) {
+                    const float mc = c.c[k];
+                    const float cl = k == 0 ? c.l : c.c[k - 1], cr = k == 3 ? c.r : c.c[k + 1];
+                    const float ul = k == 0 ? u.l : u.c[k - 1], uc = u.c[k], ur = k == 3 ? u.r : u.c[k + 1];
+                    const float dl = k == 0 ? d.l : d.c[k - 1], dc = d.c[k], dr = k == 3 ? d.r : d.c[k + 1];
+                    const float gxk = gxv[tD].v[k], gyk = gyv[tD].v[k];
+                    const float ax = fabsf(gxk), ay = fabsf(gyk);
+                    const bool domx = ax >= ay;
+                    const bool same = gxk * gyk > 0.0f;
+                    const float mn = fminf(ax, ay), mxv = fmaxf(ax, ay);
+                    const float fp = domx ? cr : dc;
+                    const float fd = same ? dr : (domx ? ur : dl);
+                    const float bp = domx ? cl : uc;
+                    const float bdg = same ? ul : (domx ? dl : ur);
+                    // with t = mn / mxv the interpolated neighbours are fp + t (fd - fp)
+                    // and bp + t (bdg - bp); both sides are scaled by mxv > 0 instead
+                    // of dividing (mxv = 0 implies mc = 0, which is never kept)
+                    const float ahead = fmaf(mn, fd - fp, fp * mxv);
+                    const float behind = fmaf(mn, bdg - bp, bp * mxv);
+                    const float ms = mc * mxv;
+                    const bool keep = mc > 0.0f && ms > behind && ms >= ahead;
+                    if (SIGNED) {
+                        sv.v[k] = keep ? mc : -mc;
+                        if (!EDGE || !bd.outR[k]) rmax = fmaxf(rmax, mc);
+                    } else {
+                        const uint32_t code = (keep && mc > a.high) ? 2u : ((keep && mc >= a.low) ? 1u : 0u);
+                        if (!EDGE || !bd.outR[k]) byte |= code << (2 * k);
+                    }
+                }
+                if (SIGNED) {
+                    // an opaque running max: otherwise the compiler may turn the chain
+                    // of maxima into one reduction at the end and keep every row's M alive
+                    mmax = fmaxf(mmax, rmax);
+                    __asm__ volatile("" : "+v"(mmax));
+                }
+                if (out_lane && (!EDGE || c0 < W)) {
+                    if (SIGNED) {
+                        // row pitch is W rounded up to 4, so the quad store stays inside the row
+                        *reinterpret_cast<float4*>(a.smag + (int64_t)n * a.spitch + c0) =
+                            make_float4(sv.v[0], sv.v[1], sv.v[2], sv.v[3]);
+                    } else {
+                        a.cls[(int64_t)n * a.cpitch + (c0 >> 2)] = (uint8_t)byte;
+                        if (a.mag) {
+                            float* mrow = a.mag + (int64_t)n * W;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) M.v[k] = sqrtf(s.v[k]);
-        fix_cols(M, bd);
-        MRowF m;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) m.c[k] = M.v[k];
-        m.l = from_left_f(M.v[3]);
-        m.r = from_right_f(M.v[0]);
-        mw[0] = mw[1]; mw[1] = mw[2];
-        mw[2] = selm(gr >= H, mw[1], m);
-        mw[1] = selm(gr == 0, m, mw[1]);
-        mw[0] = selm(gr == 0, m, mw[0]);
-        if (i < 2 * R + 4) continue;
-
-        // ---- Step 3 + thresholds: row n = gr - 1
-        const int n = gr - 1;
-        if (n < Y0 || n >= H) continue;
-        const MRowF& u = mw[0];
-        const MRowF& c = mw[1];
-        const MRowF& d = mw[2];
-        uint32_t byte = 0;
-        F4 sv;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const float mc = c.c[k];
-            const float cl = k == 0 ? c.l : c.c[k - 1], cr = k == 3 ? c.r : c.c[k + 1];
-            const float ul = k == 0 ? u.l : u.c[k - 1], uc = u.c[k], ur = k == 3 ? u.r : u.c[k + 1];
-            const float dl = k == 0 ? d.l : d.c[k - 1], dc = d.c[k], dr = k == 3 ? d.r : d.c[k + 1];
-            const float gxk = gxp.v[k], gyk = gyp.v[k];
-            const float ax = fabsf(gxk), ay = fabsf(gyk);
-            const bool domx = ax >= ay;
-            const bool same = gxk * gyk > 0.0f;
-            const float mn = fminf(ax, ay), mxv = fmaxf(ax, ay);
-            const float t = mxv > 0.0f ? mn * __builtin_amdgcn_rcpf(mxv) : 0.0f;
-            const float fp = domx ? cr : dc;
-            const float fd = same ? dr : (domx ? ur : dl);
-            const float bp = domx ? cl : uc;
-            const float bdg = same ? ul : (domx ? dl : ur);
-            const float ahead = lerpf_(fp, fd, t);
-            const float behind = lerpf_(bp, bdg, t);
-            const bool keep = mc > 0.0f && mc > behind && mc >= ahead;
-            if (SIGNED) {
-                sv.v[k] = keep ? mc : -mc;
-                if (!bd.outR[k]) mmax = fmaxf(mmax, mc);
-            } else {
-                const uint32_t code = (keep && mc > hi) ? 2u : ((keep && mc >= lo) ? 1u : 0u);
-                if (!bd.outR[k]) byte |= code << (2 * k);
-            }
-        }
-        if (out_lane && c0 < W) {
-            if (SIGNED) {
-                // row pitch is W rounded up to 4, so the quad store stays inside the row
-                *reinterpret_cast<float4*>(a.smag + (int64_t)n * a.spitch + c0) =
-                    make_float4(sv.v[0], sv.v[1], sv.v[2], sv.v[3]);
-            } else {
-                a.cls[(int64_t)n * a.cpitch + (c0 >> 2)] = (uint8_t)byte;
-                if (a.mag) {
-                    float* mrow = a.mag + (int64_t)n * W;
-#pragma unroll
-                    for (int k = 0; k < 4; ++k)
-                        if (!bd.outR[k]) mrow[c0 + k] = c.c[k];
+                            for (int k = 0; k < 4; ++k)
+                                if (!EDGE || !bd.outR[k]) mrow[c0 + k] = c.c[k];
+                        }
+                    }
                 }
             }
+        }
+
+        // ---- Step 2b: gradients and strength of row tC
+        const int tC = i - R - 3;
+        if (tC >= TG0 && tC <= TG1) {
+            F4 dm = dxv[tC - 1], dp = dxv[tC + 1], sm = sxv[tC - 1], sp = sxv[tC + 1];
+            if (EDGE) {  // rows -1 and H replicate rows 0 and H-1
+                const int y = ybase + tC;
+                dm = sel4(y == 0, dxv[tC], dm);
+                sm = sel4(y == 0, sxv[tC], sm);
+                dp = sel4(y == H - 1, dxv[tC], dp);
+                sp = sel4(y == H - 1, sxv[tC], sp);
+            }
+            F4 M;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const float gx = fmaf(2.0f, dxv[tC].v[k], dm.v[k] + dp.v[k]);
+                const float gy = sp.v[k] - sm.v[k];
+                gxv[tC].v[k] = gx;
+                gyv[tC].v[k] = gy;
+                // hardware square root: within an ulp, far inside the 1e-5 tolerance
+                M.v[k] = __builtin_amdgcn_sqrtf(fmaf(gx, gx, gy * gy));
+            }
+            if (EDGE) fix_cols(M, bd);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) mv[tC].c[k] = M.v[k];
+            mv[tC].l = from_left_f(M.v[3]);
+            mv[tC].r = from_right_f(M.v[0]);
+        }
+
+        // ---- Step 2a: Sobel row terms of row tB
+        const int tB = i - R - 1;
+        if (tB >= TB0 && tB <= TB1) {
+            const F4& B = Bv[tB];
+            const float bl = from_left_f(B.v[3]), br = from_right_f(B.v[0]);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const float xm = k == 0 ? bl : B.v[k - 1];
+                const float xp = k == 3 ? br : B.v[k + 1];
+                dxv[tB].v[k] = xp - xm;
+                sxv[tB].v[k] = fmaf(2.0f, B.v[k], xm + xp);
+            }
+        }
+
+        // ---- Step 1: Gaussian of row tA (vertical taps, then horizontal)
+        const int tA = i - R;
+        if (tA >= TB0 && tA <= TB1) {
+            F4 V;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                float acc = g[0] * in[tA].v[k];
+#pragma unroll
+                for (int j = 1; j <= R; ++j) acc = fmaf(g[j], in[tA - j].v[k] + in[tA + j].v[k], acc);
+                V.v[k] = acc;
+            }
+            float ext[4 + 2 * R];
+#pragma unroll
+            for (int e = -R; e < 4 + R; ++e) ext[e + R] = lane_ext(V, e);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                float acc = g[0] * ext[k + R];
+#pragma unroll
+                for (int j = 1; j <= R; ++j) acc = fmaf(g[j], ext[k + R - j] + ext[k + R + j], acc);
+                Bv[tA].v[k] = acc;
+            }
+            if (EDGE) fix_cols(Bv[tA], bd);
         }
     }
 
     if (SIGNED) {
-        const float wmax = out_lane ? mmax : 0.0f;
-        const uint32_t v = bc<uint32_t>(wave_max(wmax));
+        const uint32_t v = bc<uint32_t>(wave_max(out_lane ? mmax : 0.0f));
         if (lane == 0 && v) atomicMax(a.maxbits, v);
     }
+}
+
+// At least 3 waves per SIMD (<= 168 VGPRs); radii >= 6 need a longer input
+// window and are allowed 2 (<= 256 VGPRs) rather than spill.
+template <int R, int RR, bool SIGNED>
+__global__ void __launch_bounds__(kWGThreads) __attribute__((amdgpu_waves_per_eu(R >= 6 ? 2 : 3)))
+k_f32_forward(F32FwdArgs a, int strips_x, int nwaves, int fast_ok) {
+    constexpr int HL = WalkShape<R>::HL;
+    constexpr int SC = WalkShape<R>::SC;
+    constexpr int HR = WalkShape<R>::HR;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave_in_wg = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wg = xcd_remap(blockIdx.x, gridDim.x);
+    const int wave = wg * kWavesPerWG + wave_in_wg;
+    if (wave >= nwaves) return;
+    const int strip = wave % strips_x;
+    const int blk = wave / strips_x;
+    const int X0 = strip * SC;
+    const int Y0 = blk * RR;
+    const bool interior = fast_ok && X0 - 4 * HL >= 0 && X0 + SC + 4 * HL <= a.W &&
+                          Y0 - HR >= 0 && Y0 + RR + HR <= a.H;
+    if (interior)
+        f32_walk<R, RR, SIGNED, false>(a, X0, Y0, lane, fast_ok);
+    else
+        f32_walk<R, RR, SIGNED, true>(a, X0, Y0, lane, fast_ok);
 }
 
 constexpr int kRowThreads = 256;  // one workgroup walks whole rows
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
+__device__ __forceinline__ float min4(f32x4 v) { return fminf(fminf(v.x, v.y), fminf(v.z, v.w)); }
+__device__ __forceinline__ float max4(f32x4 v) { return fmaxf(fmaxf(v.x, v.y), fmaxf(v.z, v.w)); }
+
+constexpr int kRowBatch = 8;  // rows a thread reads per batch (loads in flight)
+
 // Input min and max, one (min, max) pair per workgroup written to
 // a.range[blockIdx.x] (no atomics: the walk reduces the pairs itself).
-// Workgroup b takes rows b, b + gridDim.x, ...; each thread takes float4
-// quads of a row.  Also clears the largest-strength word the walk reduces
-// into, which is safe because the walk is launched after this kernel.
+// Workgroup b owns rows b, b + gridDim.x, ...; a thread takes quad columns
+// q = threadIdx.x + 256 j of those rows, kRowBatch rows per batch so that
+// that many loads are in flight.  Also clears the largest-strength word the
+// walk reduces into, which is safe because the walk is launched after this
+// kernel.
 __global__ void __launch_bounds__(kRowThreads)
 k_f32_minmax(F32FwdArgs a, int quads_ok) {
     if (blockIdx.x == 0 && threadIdx.x == 0) *a.maxbits = 0u;
     float lo = 3.402823466e38f, hi = -3.402823466e38f;
     const int W = a.W;
-    const int nq = W >> 2;
-    for (int y = blockIdx.x; y < a.H; y += gridDim.x) {
-        const float* row = a.in + (int64_t)y * a.pitch;
-        int x0 = 0;
-        if (quads_ok) {
-            const f32x4* r4 = reinterpret_cast<const f32x4*>(row);
-            for (int q = threadIdx.x; q < nq; q += kRowThreads) {
-                const f32x4 v = r4[q];
-                lo = fminf(lo, fminf(fminf(v.x, v.y), fminf(v.z, v.w)));
-                hi = fmaxf(hi, fmaxf(fmaxf(v.x, v.y), fmaxf(v.z, v.w)));
+    const int nrows = (a.H - (int)blockIdx.x + (int)gridDim.x - 1) / (int)gridDim.x;
+    const int64_t rstride = (int64_t)gridDim.x * a.pitch;
+    const float* base = a.in + (int64_t)blockIdx.x * a.pitch;
+    if (quads_ok) {
+        const int nq = W >> 2;
+        for (int q = threadIdx.x; q < nq; q += kRowThreads) {
+            for (int k0 = 0; k0 < nrows; k0 += kRowBatch) {
+                f32x4 v[kRowBatch];
+#pragma unroll
+                for (int u = 0; u < kRowBatch; ++u)
+                    if (k0 + u < nrows) v[u] = reinterpret_cast<const f32x4*>(base + (k0 + u) * rstride)[q];
+#pragma unroll
+                for (int u = 0; u < kRowBatch; ++u) {
+                    if (k0 + u < nrows) {
+                        lo = fminf(lo, min4(v[u]));
+                        hi = fmaxf(hi, max4(v[u]));
+                    }
+                }
             }
-            x0 = 4 * nq;
         }
-        for (int x = x0 + threadIdx.x; x < W; x += kRowThreads) {
-            lo = fminf(lo, row[x]);
-            hi = fmaxf(hi, row[x]);
+        for (int x = 4 * nq + threadIdx.x; x < W; x += kRowThreads) {  // ragged tail columns
+            for (int k = 0; k < nrows; ++k) {
+                lo = fminf(lo, base[k * rstride + x]);
+                hi = fmaxf(hi, base[k * rstride + x]);
+            }
+        }
+    } else {
+        for (int x = threadIdx.x; x < W; x += kRowThreads) {
+            for (int k = 0; k < nrows; ++k) {
+                lo = fminf(lo, base[k * rstride + x]);
+                hi = fmaxf(hi, base[k * rstride + x]);
+            }
         }
     }
     __shared__ float2 part[kRowThreads / kWave];
@@ -336,8 +413,9 @@ k_f32_minmax(F32FwdArgs a, int quads_ok) {
 // Thresholds and classes from the signed strength map: a pixel is kept iff
 // its stored value is positive (M > 0 and not suppressed); then strong iff
 // M > high, weak iff M >= low, with low/high scaled by the largest M when
-// thresholds are relative.  Each thread packs 16 pixels into one 32-bit
-// word of the class map.
+// thresholds are relative.  Workgroup b owns rows b, b + gridDim.x, ...; a
+// thread takes quad columns q = threadIdx.x + 256 j (one class byte each,
+// so a wave's loads and stores are contiguous), kRowBatch rows per batch.
 __global__ void __launch_bounds__(kRowThreads)
 k_f32_classify(F32FwdArgs a) {
     const float mx = bc<float>(a.maxbits[0]);
@@ -345,58 +423,78 @@ k_f32_classify(F32FwdArgs a) {
     const float hi = a.relative ? a.high * mx : a.high;
     if (a.max_out && blockIdx.x == 0 && threadIdx.x == 0) *a.max_out = mx;
     const int W = a.W;
-    const int nq = (W + 3) >> 2;     // quads of the row (pitch holds them all)
-    const int nw = (nq + 3) >> 2;    // 16-pixel words
+    const int nq = (W + 3) >> 2;  // quads of the row (the pitch holds them all)
+    const int nrows = (a.H - (int)blockIdx.x + (int)gridDim.x - 1) / (int)gridDim.x;
     const bool mag4 = a.mag && (W % 4 == 0) && ((uintptr_t)a.mag % 16 == 0);
-    for (int y = blockIdx.x; y < a.H; y += gridDim.x) {
-        const float* srow = a.smag + (int64_t)y * a.spitch;
-        uint32_t* crow = reinterpret_cast<uint32_t*>(a.cls + (int64_t)y * a.cpitch);
-        for (int w = threadIdx.x; w < nw; w += kRowThreads) {
-            uint32_t word = 0;
+    for (int q = threadIdx.x; q < nq; q += kRowThreads) {
+        for (int k0 = 0; k0 < nrows; k0 += kRowBatch) {
+            f32x4 v[kRowBatch];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int q = 4 * w + j;
-                if (q >= nq) break;
-                const f32x4 v4 = reinterpret_cast<const f32x4*>(srow)[q];
-                const float v[4] = {v4.x, v4.y, v4.z, v4.w};
+            for (int u = 0; u < kRowBatch; ++u) {
+                const int y = (int)blockIdx.x + (k0 + u) * (int)gridDim.x;
+                if (k0 + u < nrows) v[u] = reinterpret_cast<const f32x4*>(a.smag + (int64_t)y * a.spitch)[q];
+            }
+#pragma unroll
+            for (int u = 0; u < kRowBatch; ++u) {
+                if (k0 + u >= nrows) break;
+                const int y = (int)blockIdx.x + (k0 + u) * (int)gridDim.x;
+                const float e[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+                uint32_t byte = 0;
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
-                    const int x = 4 * q + k;
-                    const uint32_t code = (x < W && v[k] > 0.0f) ? (v[k] > hi ? 2u : (v[k] >= lo ? 1u : 0u)) : 0u;
-                    word |= code << (8 * j + 2 * k);
+                    const uint32_t code =
+                        (4 * q + k < W && e[k] > 0.0f) ? (e[k] > hi ? 2u : (e[k] >= lo ? 1u : 0u)) : 0u;
+                    byte |= code << (2 * k);
                 }
+                a.cls[(int64_t)y * a.cpitch + q] = (uint8_t)byte;
                 if (a.mag) {
                     float* mrow = a.mag + (int64_t)y * W;
                     if (mag4) {
                         *reinterpret_cast<float4*>(mrow + 4 * q) =
-                            make_float4(fabsf(v[0]), fabsf(v[1]), fabsf(v[2]), fabsf(v[3]));
+                            make_float4(fabsf(e[0]), fabsf(e[1]), fabsf(e[2]), fabsf(e[3]));
                     } else {
 #pragma unroll
                         for (int k = 0; k < 4; ++k)
-                            if (4 * q + k < W) mrow[4 * q + k] = fabsf(v[k]);
+                            if (4 * q + k < W) mrow[4 * q + k] = fabsf(e[k]);
                     }
                 }
             }
-            crow[w] = word;
         }
     }
 }
 
-int rows_grid(int H) { return min(H, 8 * 256); }
+// row-owning workgroups of the classify pass: few enough that each owns a
+// full batch of rows on large images
+int rows_grid(int H) { return min(H, 512); }
+
+// One walk launch with RR output rows per wave.
+template <int R, int RR, bool SIGNED>
+void launch_walk(const F32FwdArgs& a, int fast_ok, hipStream_t s) {
+    const int strips_x = ceil_div(a.W, WalkShape<R>::SC);
+    const int nwaves = strips_x * ceil_div(a.H, RR);
+    const int nwg = ceil_div(nwaves, kWavesPerWG);
+    hipLaunchKernelGGL((k_f32_forward<R, RR, SIGNED>), dim3(nwg), dim3(kWGThreads), 0, s, a,
+                       strips_x, nwaves, fast_ok);
+}
+
+// Rows per wave: a wave walks its strip serially, so long strips suit large
+// images (halo rows amortised) and short ones small images (more waves in
+// flight).  32 unless that leaves fewer than 1024 waves (one per SIMD).
+template <int R, bool SIGNED>
+void launch_walk_sized(const F32FwdArgs& a, int fast_ok, hipStream_t s) {
+    const int strips_x = ceil_div(a.W, WalkShape<R>::SC);
+    if ((int64_t)strips_x * ceil_div(a.H, 32) >= 1024)
+        launch_walk<R, 32, SIGNED>(a, fast_ok, s);
+    else
+        launch_walk<R, 8, SIGNED>(a, fast_ok, s);
+}
 
 template <int R>
 hipError_t launch_radius(const F32FwdArgs& a, hipStream_t s) {
-    constexpr int RR = 32;
-    constexpr int HL = (R + 2 + 3) / 4;
-    constexpr int SC = 4 * (kWave - 2 * HL);
-    const int strips_x = ceil_div(a.W, SC);
-    const int nwaves = strips_x * ceil_div(a.H, RR);
-    const int nwg = ceil_div(nwaves, kWavesPerWG);
     const int fast_ok = ((uintptr_t)a.in % 16 == 0) && (a.pitch % 4 == 0);
     if (!a.smag) {  // absolute thresholds, no max: classify in the walk
         StageTimer t(CANNY_STAGE_F32_WALK, s);
-        hipLaunchKernelGGL((k_f32_forward<R, RR, false>), dim3(nwg), dim3(kWGThreads), 0, s, a,
-                           strips_x, nwaves, fast_ok);
+        launch_walk_sized<R, false>(a, fast_ok, s);
         return hipGetLastError();
     }
     F32FwdArgs b = a;
@@ -407,8 +505,7 @@ hipError_t launch_radius(const F32FwdArgs& a, hipStream_t s) {
     }
     {
         StageTimer t(CANNY_STAGE_F32_WALK, s);
-        hipLaunchKernelGGL((k_f32_forward<R, RR, true>), dim3(nwg), dim3(kWGThreads), 0, s, b,
-                           strips_x, nwaves, fast_ok);
+        launch_walk_sized<R, true>(b, fast_ok, s);
     }
     {
         StageTimer t(CANNY_STAGE_F32_CLASSIFY, s);

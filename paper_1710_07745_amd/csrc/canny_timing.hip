@@ -5,7 +5,7 @@
 #include <mutex>
 #include <vector>
 
-#include "canny.h"
+#include "../../include/canny.h"
 #include "canny_internal.h"
 
 namespace canny {

@@ -168,4 +168,5 @@ def test_float_stage_timing(canny):
             ms, n = t.read(stage)
             assert n == 3 and ms > 0.0, stage
         assert t.read("u8_forward") == (0.0, 0)
-    assert torch.equal(e, ref_e) and torch.equal(c, ref_c)
+    nb = (X.shape[1] + 3) // 4  # class bytes of a row (padding past them is unspecified)
+    assert torch.equal(e, ref_e) and torch.equal(c[:, :nb], ref_c[:, :nb])
