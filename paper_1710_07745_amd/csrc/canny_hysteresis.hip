@@ -12,25 +12,30 @@
 //              joins N, or NW and NE when N is empty; a later pixel joins NE
 //              only when N is empty) -- the same components as joining every
 //              8-neighbour, with about one union per run instead of four per
-//              pixel.  Links use atomicMin (roots = smallest pixel index) and
-//              the forest is flattened by pointer jumping.  A component is
-//              named globally by tile * 64T + its root.  The pass writes, per
-//              tile-border pixel, the global name of its component (or -1),
-//              initialises parent/flag for every component that touches the
-//              border (sparse arrays indexed by global name), and writes one
-//              16-bit record per pixel: bit 15 candidate, bit 14 component
-//              holds a strong pixel of this tile, bits 0..11 the local root.
+//              pixel.  Links use atomicMin (roots = smallest pixel index);
+//              once all unions are in, every run start finds its root with a
+//              read-only walk.  A component that does not touch the tile
+//              border is decided here: its pixels get 255 if it holds a
+//              strong pixel, else 0.  A component that touches the border is
+//              named globally by tile * 64T + its root; the pass writes, per
+//              tile-border pixel, that name (or -1), initialises parent/flag
+//              for it (sparse arrays indexed by name), and gives its pixels
+//              the pending code 1 + b, b (0..251) the index of one of the
+//              component's border pixels.  Non-candidates get 0.
 //   2. merge:  one thread per tile-border pixel on the right and bottom tile
 //              edges unions its component with the 8-connected candidates
 //              across the edge (global union-find, atomicMin linking).
 //   3. flags:  one thread per border slot finds its component's root
 //              (read-only walk), stores it (flattening the forest) and ORs the
 //              component's strong flag into the root's.
-//   4. final:  each workgroup gathers the root flags of its border
-//              components into LDS and turns the per-pixel records into
-//              255 / 0.
+//   4. resolve: each workgroup rewrites the pending pixels of its tile to
+//              255 / 0 from the flag of the root named by the border pixel
+//              the code points at.
 // Border slots of a tile (clipped to the image): top row x -> x, bottom row
 // x -> 64 + x, left column y -> 128 + y, right column y -> 128 + T + y.
+// Border pixel index b (each border pixel once, for the pending code): top
+// row x -> x, bottom row x -> 64 + x, left column y (not top or bottom) ->
+// 127 + y, right column y -> 189 + y.
 #include "canny_internal.h"
 
 namespace canny {
@@ -203,23 +208,22 @@ __device__ __forceinline__ TileLabel<T> tile_label(const uint8_t* cls, int64_t c
         }
     }
     __syncthreads();
-    // flatten the run starts by pointer jumping (each round at least halves
-    // every depth; the reads of one thread are independent)
+    // all unions are in: each run start walks to its root (pointers only
+    // decrease, so within i + 1 steps) and stores it.  Concurrent walks read
+    // either an old pointer (an ancestor) or a root, so no store can mislead
+    // another walk.
     volatile int* V = L;
-    // depth <= 4096 halves each round: 13 rounds always suffice
-    for (int round = 0; round < 16; ++round) {
-        bool changed = false;
-        for (uint64_t b = Smine; b; b &= b - 1) {
-            const int i = r * kHystCols + __ffsll((long long)b) - 1;
-            const int p = V[i];
-            const int q = V[p];
-            if (q != p) {
-                V[i] = q;
-                changed = true;
-            }
+    for (uint64_t b = Smine; b; b &= b - 1) {
+        const int i = r * kHystCols + __ffsll((long long)b) - 1;
+        int x = V[i];
+        for (int steps = i; steps >= 0; --steps) {
+            const int p = V[x];
+            if (p == x) break;
+            x = p;
         }
-        if (!__syncthreads_or(changed)) break;
+        V[i] = x;
     }
+    __syncthreads();
     return st;
 }
 
@@ -237,69 +241,117 @@ struct LocalSmem {
     int L[Tile<T>::kPx];
     uint64_t cm[T];               // candidate mask of each tile row
     uint8_t sfl[Tile<T>::kPx];    // component (by root) holds a strong pixel
+    uint8_t brep[Tile<T>::kPx];   // component (by root) touches the border: 1 + b, else 0
     int bl[Tile<T>::kPerim];      // staged border names: one global store per slot
 };
 
+// border pixel index b of tile pixel (r, c), or -1 inside (see the file comment)
+__device__ __forceinline__ int border_index(int r, int c, int th, int tw) {
+    if (r == 0) return c;
+    if (r == th - 1) return kHystCols + c;
+    if (c == 0) return 2 * kHystCols - 1 + r;
+    if (c == tw - 1) return 3 * kHystCols - 3 + r;
+    return -1;
+}
+
+// the border slot holding the global name of border pixel index b
+template <int T>
+__device__ __forceinline__ int border_slot(int b) {
+    if (b < 2 * kHystCols) return b;                                      // top / bottom row
+    if (b < 3 * kHystCols - 2) return 2 * kHystCols + (b - 2 * kHystCols + 1);  // left column
+    return 2 * kHystCols + T + (b - (3 * kHystCols - 2) + 1);               // right column
+}
+
+// A thread's 16 output bytes (row segment of a tile) as two little-endian
+// 64-bit words; byte k is pixel k.  Helpers take compile-time or run-time k
+// without a dynamically indexed array (which would live in scratch or LDS).
+struct Seg16 {
+    uint64_t lo = 0, hi = 0;
+    __device__ __forceinline__ uint32_t get(int k) const {
+        return (uint32_t)((k < 8 ? lo >> (8 * k) : hi >> (8 * (k - 8))) & 0xFFu);
+    }
+    __device__ __forceinline__ void set(int k, uint32_t v) {  // byte k must be 0
+        if (k < 8) lo |= (uint64_t)v << (8 * k);
+        else hi |= (uint64_t)v << (8 * (k - 8));
+    }
+    __device__ __forceinline__ void put(int k, uint32_t v) {
+        if (k < 8) lo = (lo & ~(0xFFull << (8 * k))) | ((uint64_t)v << (8 * k));
+        else hi = (hi & ~(0xFFull << (8 * (k - 8)))) | ((uint64_t)v << (8 * (k - 8)));
+    }
+};
+
+__device__ __forceinline__ void store_seg(uint8_t* dst, const Seg16& o, int valid, int vec16) {
+    if (vec16 && valid == 16) {
+        *reinterpret_cast<uint4*>(dst) = make_uint4((uint32_t)o.lo, (uint32_t)(o.lo >> 32),
+                                                     (uint32_t)o.hi, (uint32_t)(o.hi >> 32));
+    } else {
+        for (int k = 0; k < valid; ++k) dst[k] = (uint8_t)o.get(k);
+    }
+}
+
 // Pass 1 on one tile (the whole workgroup takes part).
 template <int T>
-__device__ __forceinline__ void local_tile(const HystArgs& a, int tile, int tiles_x, LocalSmem<T>& sm) {
+__device__ __forceinline__ void local_tile(const HystArgs& a, int tile, int tiles_x, int vec16,
+                                           LocalSmem<T>& sm) {
     using TL = Tile<T>;
+    static_assert(T <= kHystCols, "border pixel indices assume T <= 64");
     int* L = sm.L;
-    uint64_t* cm = sm.cm;
     uint8_t* sfl = sm.sfl;
+    uint8_t* brep = sm.brep;
     int* bl = sm.bl;
     const TileGeom g = tile_geom<T>(tile, tiles_x, a.H, a.W);
     const int t = threadIdx.x;
-    for (int i = t; i < TL::kPx / 4; i += kWGThreads) reinterpret_cast<uint32_t*>(sfl)[i] = 0u;
+    for (int i = t; i < TL::kPx / 4; i += kWGThreads) {
+        reinterpret_cast<uint32_t*>(sfl)[i] = 0u;
+        reinterpret_cast<uint32_t*>(brep)[i] = 0u;
+    }
     for (int s = t; s < TL::kPerim; s += kWGThreads) bl[s] = -1;  // "no candidate"
-    const TileLabel<T> st = tile_label<T>(a.cls, a.cpitch, a.W, g, L, cm);
+    const TileLabel<T> st = tile_label<T>(a.cls, a.cpitch, a.W, g, L, sm.cm);
     const int r = t / TL::kTPR;
     const int cb = (t % TL::kTPR) * TL::kPPT;
     const int me = r * kHystCols;
-    const int64_t gbase = (int64_t)g.tile * TL::kPx;
     for (uint32_t b = st.strong; b; b &= b - 1) {
         const int c = cb + __ffs(b) - 1;
         sfl[L[me + run_start(st.S, c)]] = 1;
     }
     __syncthreads();
-    uint32_t rec[TL::kPPT];
-#pragma unroll
-    for (int k = 0; k < TL::kPPT; ++k) rec[k] = 0;
+    // border pixels: name the component globally and point it at a border index
     const bool edge_row = r == 0 || r == g.th - 1;
-    for (uint32_t b = st.cand; b; b &= b - 1) {
-        const int k = __ffs(b) - 1;
-        const int c = cb + k;
-        const int root = L[me + run_start(st.S, c)];
-        const int sf = sfl[root];
-        rec[k] = 0x8000u | (sf ? 0x4000u : 0u) | (uint32_t)root;
-        if (edge_row || c == 0 || c == g.tw - 1) {
+    if (edge_row || cb == 0 || cb + TL::kPPT >= g.tw) {
+        const int64_t gbase = (int64_t)g.tile * TL::kPx;
+        for (uint32_t b = st.cand; b; b &= b - 1) {
+            const int c = cb + __ffs(b) - 1;
+            const int bi = border_index(r, c, g.th, g.tw);
+            if (bi < 0) continue;
+            const int root = L[me + run_start(st.S, c)];
             const int64_t gid = gbase + root;
             // every border pixel of the component stores the same values
             a.parent[gid] = (int)gid;
-            a.flag[gid] = sf;
+            a.flag[gid] = sfl[root];
+            brep[root] = (uint8_t)(1 + bi);  // any one of them wins
             for_slots<T>(r, c, g.th, g.tw, [&](int s) { bl[s] = (int)gid; });
         }
     }
-    // records of the tile are contiguous: this thread's PPT pixels at t * PPT
-    uint16_t* dst = a.rec + gbase + t * TL::kPPT;
-#pragma unroll
-    for (int k = 0; k < TL::kPPT; k += 8) {
-        uint4 v;
-        v.x = rec[k] | rec[k + 1] << 16;
-        v.y = rec[k + 2] | rec[k + 3] << 16;
-        v.z = rec[k + 4] | rec[k + 5] << 16;
-        v.w = rec[k + 6] | rec[k + 7] << 16;
-        *reinterpret_cast<uint4*>(dst + k) = v;
-    }
     __syncthreads();
+    if (r < g.th) {
+        Seg16 out;
+        for (uint32_t b = st.cand; b; b &= b - 1) {
+            const int k = __ffs(b) - 1;
+            const int root = L[me + run_start(st.S, cb + k)];
+            const uint32_t br = brep[root];
+            out.set(k, br ? br : (sfl[root] ? 255u : 0u));
+        }
+        const int valid = min(a.W - (g.X0 + cb), TL::kPPT);
+        if (valid > 0) store_seg(a.edges + (int64_t)(g.Y0 + r) * a.epitch + g.X0 + cb, out, valid, vec16);
+    }
     const int base = g.tile * TL::kPerim;
     for (int s = t; s < TL::kPerim; s += kWGThreads) a.blab[base + s] = bl[s];
 }
 
 template <int T>
-__global__ void __launch_bounds__(kWGThreads) k_hyst_local(HystArgs a, int tiles_x) {
+__global__ void __launch_bounds__(kWGThreads) k_hyst_local(HystArgs a, int tiles_x, int vec16) {
     __shared__ LocalSmem<T> sm;
-    local_tile<T>(a, blockIdx.x, tiles_x, sm);
+    local_tile<T>(a, blockIdx.x, tiles_x, vec16, sm);
 }
 
 // Pass 2 for border pixel k of a tile (k < T: right edge row k; else bottom
@@ -369,65 +421,54 @@ __global__ void __launch_bounds__(kWGThreads) k_hyst_flags(HystArgs a, int nslot
     if (s < nslots) flags_one(a, s);
 }
 
-// Pass 4 on one tile; gflag: LDS, global strong flag of border components by
-// local root.
+// Pass 4 on one tile: pending codes 1..252 become 255 / 0 by the global flag
+// of their component; everything else is already final.  The workgroup first
+// resolves every border pixel index once (res: LDS, 252 entries), so each
+// pending pixel costs one LDS read; a tile without border components is left
+// untouched.
 template <int T>
-__device__ __forceinline__ void final_tile(const HystArgs& a, int tile, int tiles_x, int vec16,
-                                           uint8_t* gflag) {
+__device__ __forceinline__ void resolve_tile(const HystArgs& a, int tile, int tiles_x, int vec16,
+                                             uint8_t* res) {
     using TL = Tile<T>;
+    static_assert(kWGThreads >= 3 * kHystCols + T - 4, "one thread per border pixel index");
     const TileGeom g = tile_geom<T>(tile, tiles_x, a.H, a.W);
     const int t = threadIdx.x;
     const int base = g.tile * TL::kPerim;
-    const int64_t gbase = (int64_t)g.tile * TL::kPx;
-    for (int i = t; i < TL::kPx / 4; i += kWGThreads) reinterpret_cast<uint32_t*>(gflag)[i] = 0u;
-    __syncthreads();
-    for (int s = t; s < TL::kPerim; s += kWGThreads) {
-        const int gl = a.blab[base + s];
-        if (gl >= 0 && a.flag[a.parent[gl]]) gflag[gl - gbase] = 1;
+    bool named = false;
+    if (t < 2 * kHystCols + 2 * (T - 2)) {
+        const int gid = a.blab[base + border_slot<T>(t)];
+        named = gid >= 0;
+        res[t] = named && a.flag[a.parent[gid]] ? 255 : 0;
     }
+    if (!__syncthreads_or(named)) return;  // no border component: nothing pending
     const int r = t / TL::kTPR;
     const int cb = (t % TL::kTPR) * TL::kPPT;
-    const uint16_t* src = a.rec + (int64_t)g.tile * TL::kPx + t * TL::kPPT;
-    uint32_t w[TL::kPPT / 2];
-#pragma unroll
-    for (int k = 0; k < TL::kPPT; k += 8) {
-        const uint4 v = *reinterpret_cast<const uint4*>(src + k);
-        w[k / 2] = v.x; w[k / 2 + 1] = v.y; w[k / 2 + 2] = v.z; w[k / 2 + 3] = v.w;
+    const int valid = min(a.W - (g.X0 + cb), TL::kPPT);
+    if (r >= g.th || valid <= 0) return;
+    uint8_t* dst = a.edges + (int64_t)(g.Y0 + r) * a.epitch + g.X0 + cb;
+    Seg16 out;
+    if (vec16 && valid == TL::kPPT) {
+        const uint4 v = *reinterpret_cast<const uint4*>(dst);
+        out.lo = v.x | (uint64_t)v.y << 32;
+        out.hi = v.z | (uint64_t)v.w << 32;
+    } else {
+        for (int k = 0; k < valid; ++k) out.set(k, dst[k]);
     }
-    __syncthreads();
-    if (r >= g.th) return;  // no barrier follows in this function
-    uint8_t out[TL::kPPT];
+    bool any = false;
 #pragma unroll
     for (int k = 0; k < TL::kPPT; ++k) {
-        const uint32_t q = (w[k / 2] >> (16 * (k & 1))) & 0xFFFFu;
-        const bool strong = (q & 0x4000u) || gflag[q & 0xFFFu];
-        out[k] = ((q & 0x8000u) && strong) ? 255 : 0;
+        const uint32_t e = out.get(k);
+        if (e == 0 || e == 255) continue;  // final already (bytes past `valid` are 0)
+        out.put(k, res[e - 1]);
+        any = true;
     }
-    uint8_t* dst = a.edges + (int64_t)(g.Y0 + r) * a.epitch + g.X0 + cb;
-    const int valid = min(a.W - (g.X0 + cb), TL::kPPT);
-    if (vec16 && valid == TL::kPPT) {
-        if constexpr (TL::kPPT == 16) {
-            uint4 v;
-            v.x = out[0] | out[1] << 8 | out[2] << 16 | (uint32_t)out[3] << 24;
-            v.y = out[4] | out[5] << 8 | out[6] << 16 | (uint32_t)out[7] << 24;
-            v.z = out[8] | out[9] << 8 | out[10] << 16 | (uint32_t)out[11] << 24;
-            v.w = out[12] | out[13] << 8 | out[14] << 16 | (uint32_t)out[15] << 24;
-            *reinterpret_cast<uint4*>(dst) = v;
-        } else {
-            uint2 v;
-            v.x = out[0] | out[1] << 8 | out[2] << 16 | (uint32_t)out[3] << 24;
-            v.y = out[4] | out[5] << 8 | out[6] << 16 | (uint32_t)out[7] << 24;
-            *reinterpret_cast<uint2*>(dst) = v;
-        }
-    } else {
-        for (int k = 0; k < valid; ++k) dst[k] = out[k];
-    }
+    if (any) store_seg(dst, out, valid, vec16);
 }
 
 template <int T>
-__global__ void __launch_bounds__(kWGThreads) k_hyst_final(HystArgs a, int tiles_x, int vec16) {
-    __shared__ uint8_t gflag[Tile<T>::kPx];
-    final_tile<T>(a, blockIdx.x, tiles_x, vec16, gflag);
+__global__ void __launch_bounds__(kWGThreads) k_hyst_resolve(HystArgs a, int tiles_x, int vec16) {
+    __shared__ uint8_t res[kWGThreads];
+    resolve_tile<T>(a, blockIdx.x, tiles_x, vec16, res);
 }
 
 template <int T>
@@ -438,13 +479,13 @@ hipError_t launch_t(const HystArgs& a, hipStream_t s) {
     const int ntiles = tiles_x * tiles_y;
     const int nslots = ntiles * TL::kPerim;
     const int vec16 = ((uintptr_t)a.edges % 16 == 0) && (a.epitch % 16 == 0);
-    hipLaunchKernelGGL(k_hyst_local<T>, dim3(ntiles), dim3(kWGThreads), 0, s, a, tiles_x);
+    hipLaunchKernelGGL(k_hyst_local<T>, dim3(ntiles), dim3(kWGThreads), 0, s, a, tiles_x, vec16);
     const int64_t nmerge = (int64_t)ntiles * (T + kHystCols);
     hipLaunchKernelGGL(k_hyst_merge<T>, dim3((unsigned)ceil_div64(nmerge, kWGThreads)),
                        dim3(kWGThreads), 0, s, a, tiles_x, tiles_y, ntiles);
     hipLaunchKernelGGL(k_hyst_flags, dim3(ceil_div(nslots, kWGThreads)), dim3(kWGThreads), 0, s,
                        a, nslots);
-    hipLaunchKernelGGL(k_hyst_final<T>, dim3(ntiles), dim3(kWGThreads), 0, s, a, tiles_x, vec16);
+    hipLaunchKernelGGL(k_hyst_resolve<T>, dim3(ntiles), dim3(kWGThreads), 0, s, a, tiles_x, vec16);
     return hipGetLastError();
 }
 
@@ -460,7 +501,6 @@ __device__ __forceinline__ HystArgs batch_args(const BatchImage& im, char* ws) {
     a.blab = reinterpret_cast<int32_t*>(ws + im.blab_off);
     a.parent = reinterpret_cast<int32_t*>(ws + im.parent_off);
     a.flag = reinterpret_cast<int32_t*>(ws + im.flag_off);
-    a.rec = reinterpret_cast<uint16_t*>(ws + im.rec_off);
     return a;
 }
 
@@ -490,7 +530,8 @@ k_hyst_local_batch(const BatchImage* imgs, const BatchDev* hdr, uint32_t* counte
         if (task >= total) break;
         const int i = batch_find(imgs, n, task, [](const BatchImage& m) { return m.tile_base; });
         const BatchImage& im = imgs[i];
-        local_tile<T>(batch_args(im, ws), task - im.tile_base, im.tiles_x, sm);
+        const int vec16 = ((uintptr_t)im.edges % 16 == 0) && (im.epitch % 16 == 0);
+        local_tile<T>(batch_args(im, ws), task - im.tile_base, im.tiles_x, vec16, sm);
         __syncthreads();  // LDS and task_s are reused by the next tile
     }
 }
@@ -515,8 +556,8 @@ __global__ void __launch_bounds__(kWGThreads) k_hyst_flags_batch(const BatchImag
 
 template <int T>
 __global__ void __launch_bounds__(kWGThreads)
-k_hyst_final_batch(const BatchImage* imgs, const BatchDev* hdr, uint32_t* counter) {
-    __shared__ uint8_t gflag[Tile<T>::kPx];
+k_hyst_resolve_batch(const BatchImage* imgs, const BatchDev* hdr, uint32_t* counter) {
+    __shared__ uint8_t res[kWGThreads];
     __shared__ int task_s;
     const int n = hdr->n, total = hdr->total_tiles;
     char* ws = hdr->ws;
@@ -528,8 +569,8 @@ k_hyst_final_batch(const BatchImage* imgs, const BatchDev* hdr, uint32_t* counte
         const int i = batch_find(imgs, n, task, [](const BatchImage& m) { return m.tile_base; });
         const BatchImage& im = imgs[i];
         const int vec16 = ((uintptr_t)im.edges % 16 == 0) && (im.epitch % 16 == 0);
-        final_tile<T>(batch_args(im, ws), task - im.tile_base, im.tiles_x, vec16, gflag);
-        __syncthreads();
+        resolve_tile<T>(batch_args(im, ws), task - im.tile_base, im.tiles_x, vec16, res);
+        __syncthreads();  // res and task_s are reused by the next tile
     }
 }
 
@@ -543,7 +584,7 @@ hipError_t launch_hyst_batch(const BatchImage* imgs, const BatchDev* hdr, uint32
                        dim3(kWGThreads), 0, s, imgs, hdr);
     hipLaunchKernelGGL(k_hyst_flags_batch, dim3(ceil_div(max(total_slots, 1), kWGThreads)),
                        dim3(kWGThreads), 0, s, imgs, hdr);
-    hipLaunchKernelGGL(k_hyst_final_batch<T>, dim3(nwg), dim3(kWGThreads), 0, s, imgs, hdr, counters + 1);
+    hipLaunchKernelGGL(k_hyst_resolve_batch<T>, dim3(nwg), dim3(kWGThreads), 0, s, imgs, hdr, counters + 1);
     return hipGetLastError();
 }
 
@@ -554,11 +595,11 @@ static int perim(int tile_rows) { return 2 * kHystCols + 2 * tile_rows; }
 static size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 // blab: int32 per border slot; parent, flag: int32 per tile pixel (sparsely
-// touched: only entries named by a border component); rec: uint16 per pixel
+// touched: only entries named by a border component)
 size_t hyst_workspace_bytes(int H, int W, int tile_rows) {
     const size_t ntiles = (size_t)ceil_div(W, kHystCols) * ceil_div(H, tile_rows);
     const size_t npx = ntiles * (size_t)kHystCols * tile_rows;
-    return al256(ntiles * perim(tile_rows) * 4) + 2 * al256(npx * 4) + al256(npx * 2);
+    return al256(ntiles * perim(tile_rows) * 4) + 2 * al256(npx * 4);
 }
 
 void hyst_carve(void* ws, int H, int W, int tile_rows, HystArgs& a) {
@@ -570,8 +611,6 @@ void hyst_carve(void* ws, int H, int W, int tile_rows, HystArgs& a) {
     a.parent = reinterpret_cast<int32_t*>(p);
     p += al256(npx * 4);
     a.flag = reinterpret_cast<int32_t*>(p);
-    p += al256(npx * 4);
-    a.rec = reinterpret_cast<uint16_t*>(p);
 }
 
 hipError_t launch_hysteresis(const HystArgs& a, int tile_rows, hipStream_t s) {

@@ -86,7 +86,6 @@ struct HystArgs {
     int32_t* blab;    // [ntiles * perim] global component name of each border pixel
     int32_t* parent;  // [ntiles * 64T] union-find forest over component names (sparse)
     int32_t* flag;    // [ntiles * 64T] strong flags (sparse)
-    uint16_t* rec;    // [ntiles * 64 * T] per-pixel records, tile-major
 };
 int hyst_tile_rows_default();
 size_t hyst_workspace_bytes(int H, int W, int tile_rows);
@@ -137,7 +136,7 @@ struct BatchImage {
     int64_t epitch;
     int H, W;
     int64_t cpitch;
-    int64_t cls_off, blab_off, parent_off, flag_off, rec_off;  // bytes into the workspace
+    int64_t cls_off, blab_off, parent_off, flag_off;  // bytes into the workspace
     int fwd_strips_x, fwd_base;  // forward wave tasks before this image
     int tiles_x, tiles_y, tile_base;
     int merge_base, slot_base;
