@@ -236,12 +236,18 @@ __device__ __forceinline__ void for_slots(int r, int c, int th, int tw, F f) {
     if (c == tw - 1) f(2 * kHystCols + T + r);
 }
 
+// L[i] for a run start i: the pixel index of its root (bits 0..11) once the
+// labels are final.  A root's own entry then also carries its component's
+// flags: bit 16 = holds a strong pixel, bits 17..24 = 1 + b for some border
+// pixel index b of the component (0: does not touch the tile border).
+constexpr int kRootMask = 0xFFFF;
+constexpr int kStrongBit = 1 << 16;
+constexpr int kBrepShift = 17;
+
 template <int T>
 struct LocalSmem {
     int L[Tile<T>::kPx];
     uint64_t cm[T];               // candidate mask of each tile row
-    uint8_t sfl[Tile<T>::kPx];    // component (by root) holds a strong pixel
-    uint8_t brep[Tile<T>::kPx];   // component (by root) touches the border: 1 + b, else 0
     int bl[Tile<T>::kPerim];      // staged border names: one global store per slot
 };
 
@@ -296,15 +302,9 @@ __device__ __forceinline__ void local_tile(const HystArgs& a, int tile, int tile
     using TL = Tile<T>;
     static_assert(T <= kHystCols, "border pixel indices assume T <= 64");
     int* L = sm.L;
-    uint8_t* sfl = sm.sfl;
-    uint8_t* brep = sm.brep;
     int* bl = sm.bl;
     const TileGeom g = tile_geom<T>(tile, tiles_x, a.H, a.W);
     const int t = threadIdx.x;
-    for (int i = t; i < TL::kPx / 4; i += kWGThreads) {
-        reinterpret_cast<uint32_t*>(sfl)[i] = 0u;
-        reinterpret_cast<uint32_t*>(brep)[i] = 0u;
-    }
     for (int s = t; s < TL::kPerim; s += kWGThreads) bl[s] = -1;  // "no candidate"
     const TileLabel<T> st = tile_label<T>(a.cls, a.cpitch, a.W, g, L, sm.cm);
     const int r = t / TL::kTPR;
@@ -312,7 +312,7 @@ __device__ __forceinline__ void local_tile(const HystArgs& a, int tile, int tile
     const int me = r * kHystCols;
     for (uint32_t b = st.strong; b; b &= b - 1) {
         const int c = cb + __ffs(b) - 1;
-        sfl[L[me + run_start(st.S, c)]] = 1;
+        atomicOr(&L[L[me + run_start(st.S, c)] & kRootMask], kStrongBit);
     }
     __syncthreads();
     // border pixels: name the component globally and point it at a border index
@@ -323,12 +323,13 @@ __device__ __forceinline__ void local_tile(const HystArgs& a, int tile, int tile
             const int c = cb + __ffs(b) - 1;
             const int bi = border_index(r, c, g.th, g.tw);
             if (bi < 0) continue;
-            const int root = L[me + run_start(st.S, c)];
+            const int root = L[me + run_start(st.S, c)] & kRootMask;
+            const int low = root | (L[root] & kStrongBit);  // final: no strong marks remain
             const int64_t gid = gbase + root;
             // every border pixel of the component stores the same values
             a.parent[gid] = (int)gid;
-            a.flag[gid] = sfl[root];
-            brep[root] = (uint8_t)(1 + bi);  // any one of them wins
+            a.flag[gid] = low >> 16;
+            atomicMax(&L[root], low | ((1 + bi) << kBrepShift));  // the largest index wins
             for_slots<T>(r, c, g.th, g.tw, [&](int s) { bl[s] = (int)gid; });
         }
     }
@@ -337,9 +338,9 @@ __device__ __forceinline__ void local_tile(const HystArgs& a, int tile, int tile
         Seg16 out;
         for (uint32_t b = st.cand; b; b &= b - 1) {
             const int k = __ffs(b) - 1;
-            const int root = L[me + run_start(st.S, cb + k)];
-            const uint32_t br = brep[root];
-            out.set(k, br ? br : (sfl[root] ? 255u : 0u));
+            const int v = L[L[me + run_start(st.S, cb + k)] & kRootMask];
+            const uint32_t br = (uint32_t)v >> kBrepShift;
+            out.set(k, br ? br : ((v & kStrongBit) ? 255u : 0u));
         }
         const int valid = min(a.W - (g.X0 + cb), TL::kPPT);
         if (valid > 0) store_seg(a.edges + (int64_t)(g.Y0 + r) * a.epitch + g.X0 + cb, out, valid, vec16);
@@ -433,19 +434,12 @@ __device__ __forceinline__ void resolve_tile(const HystArgs& a, int tile, int ti
     static_assert(kWGThreads >= 3 * kHystCols + T - 4, "one thread per border pixel index");
     const TileGeom g = tile_geom<T>(tile, tiles_x, a.H, a.W);
     const int t = threadIdx.x;
-    const int base = g.tile * TL::kPerim;
-    bool named = false;
-    if (t < 2 * kHystCols + 2 * (T - 2)) {
-        const int gid = a.blab[base + border_slot<T>(t)];
-        named = gid >= 0;
-        res[t] = named && a.flag[a.parent[gid]] ? 255 : 0;
-    }
-    if (!__syncthreads_or(named)) return;  // no border component: nothing pending
     const int r = t / TL::kTPR;
     const int cb = (t % TL::kTPR) * TL::kPPT;
-    const int valid = min(a.W - (g.X0 + cb), TL::kPPT);
-    if (r >= g.th || valid <= 0) return;
+    const int valid = r < g.th ? min(a.W - (g.X0 + cb), TL::kPPT) : 0;
     uint8_t* dst = a.edges + (int64_t)(g.Y0 + r) * a.epitch + g.X0 + cb;
+    // the segment's bytes are read first so that their latency overlaps the
+    // lookups below
     Seg16 out;
     if (vec16 && valid == TL::kPPT) {
         const uint4 v = *reinterpret_cast<const uint4*>(dst);
@@ -454,6 +448,14 @@ __device__ __forceinline__ void resolve_tile(const HystArgs& a, int tile, int ti
     } else {
         for (int k = 0; k < valid; ++k) out.set(k, dst[k]);
     }
+    const int base = g.tile * TL::kPerim;
+    bool named = false;
+    if (t < 2 * kHystCols + 2 * (T - 2)) {
+        const int gid = a.blab[base + border_slot<T>(t)];
+        named = gid >= 0;
+        res[t] = named && a.flag[a.parent[gid]] ? 255 : 0;
+    }
+    if (!__syncthreads_or(named)) return;  // no border component: nothing pending
     bool any = false;
 #pragma unroll
     for (int k = 0; k < TL::kPPT; ++k) {
