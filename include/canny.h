@@ -142,9 +142,10 @@ int canny_f32(const float* in, int64_t in_pitch, int H, int W, float sigma, int 
  * plan fixes the image sizes and thresholds, picks tile shapes (from an
  * on-disk autotune cache, by timing candidates when autotune != 0, else a
  * default), and records one HIP graph whose kernels each cover every tile
- * of every image in a single persistent launch (a device-side tile counter
- * hands out work).  canny_batch writes the per-image pointer table to the
- * device and replays the graph on `stream`.
+ * of every image in a single persistent launch (each persistent wave or
+ * workgroup takes a contiguous share of the batch's strips or tiles).
+ * canny_batch writes the per-image pointer table to the device and replays
+ * the graph on `stream`.
  *
  * canny_batch_plan_create: n >= 1; H, W host arrays of n sizes (>= 1 each);
  *   0 <= low <= high; *out receives a host-owned plan.  May allocate device

@@ -4,11 +4,12 @@
 // A plan fixes the sizes and thresholds and lays out one workspace region per
 // image (class map + hysteresis state).  Every phase of the detector runs as
 // ONE launch over all images: the forward and the two per-tile hysteresis
-// passes are persistent kernels whose waves / workgroups claim (image, tile)
-// work items from device counters, so large and small images interleave
-// freely; the two per-border-pixel passes are flat grids over all images.
-// The launches are recorded once into a HIP graph
-//     [reset counters] -> forward -> local -> merge -> flags -> final
+// passes are persistent kernels: each wave (forward) or workgroup (tiles)
+// takes a contiguous share of the batch's work items, which are uniform
+// strips / tiles, so large and small images interleave freely and no shared
+// counter is touched; the two per-border-pixel passes are flat grids over
+// all images.  The launches are recorded once into a HIP graph
+//     forward -> local -> merge -> flags -> resolve
 // whose kernels read a device descriptor table; a call uploads the table
 // (the caller's image pointers and workspace) and replays the graph, so new
 // buffers never need a new recording.
@@ -52,7 +53,6 @@ struct canny_batch_plan {
     BatchDev hdr{};
     BatchImage* d_imgs = nullptr;
     BatchDev* d_hdr = nullptr;
-    uint32_t* d_counters = nullptr;
     BatchImage* h_stage = nullptr;  // pinned staging of the descriptor table
     BatchDev* h_stage_hdr = nullptr;
     hipEvent_t uploaded = nullptr;
@@ -67,10 +67,6 @@ constexpr int kT = 64;  // hysteresis tile rows
 constexpr int kPerimT = 2 * kHystCols + 2 * kT;
 
 size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
-
-__global__ void k_batch_reset(uint32_t* c) {
-    if (threadIdx.x < 4) c[threadIdx.x] = 0u;
-}
 
 // deterministic texture for tuning runs: smooth ramps plus hashed noise
 __global__ void k_fill_texture(uint8_t* p, int64_t n, uint32_t seed) {
@@ -134,11 +130,9 @@ void set_fwd_rows(canny_batch_plan& p, int rows) {
 
 hipError_t enqueue(const canny_batch_plan& p, hipStream_t s) {
     const int nwg = p.cus * p.wgs_per_cu;
-    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, p.d_counters);
-    hipError_t e = launch_u8_forward_batch(p.d_imgs, p.d_hdr, p.d_counters + 2, p.fwd_rows, nwg, s);
+    hipError_t e = launch_u8_forward_batch(p.d_imgs, p.d_hdr, p.fwd_rows, nwg, s);
     if (e != hipSuccess) return e;
-    return launch_hyst_batch(p.d_imgs, p.d_hdr, p.d_counters, p.hdr.total_merge, p.hdr.total_slots,
-                             nwg, s);
+    return launch_hyst_batch(p.d_imgs, p.d_hdr, p.hdr.total_merge, p.hdr.total_slots, nwg, s);
 }
 
 // synchronous upload of the table (plan creation and tuning only)
@@ -280,7 +274,6 @@ void release(canny_batch_plan* p) {
     if (p->uploaded) hipEventDestroy(p->uploaded);
     if (p->d_imgs) hipFree(p->d_imgs);
     if (p->d_hdr) hipFree(p->d_hdr);
-    if (p->d_counters) hipFree(p->d_counters);
     if (p->h_stage) hipHostFree(p->h_stage);
     if (p->h_stage_hdr) hipHostFree(p->h_stage_hdr);
     delete p;
@@ -322,7 +315,6 @@ int canny_batch_plan_create(int n, const int32_t* H, const int32_t* W, int32_t l
     set_fwd_rows(*p, 32);
     e = hipMalloc(&p->d_imgs, sizeof(BatchImage) * n);
     if (e == hipSuccess) e = hipMalloc(&p->d_hdr, sizeof(BatchDev));
-    if (e == hipSuccess) e = hipMalloc(&p->d_counters, 4 * sizeof(uint32_t));
     if (e == hipSuccess) e = hipHostMalloc(&p->h_stage, sizeof(BatchImage) * n, hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc(&p->h_stage_hdr, sizeof(BatchDev), hipHostMallocDefault);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&p->uploaded, hipEventDisableTiming);

@@ -518,31 +518,58 @@ __device__ __forceinline__ int batch_find(const BatchImage* imgs, int n, int v, 
     return lo;
 }
 
+// image of item v for a run of increasing items: start from the image of the
+// previous item (i) and step forward (at most n - 1 steps in total)
+template <typename Get>
+__device__ __forceinline__ int batch_advance(const BatchImage* imgs, int n, int i, int v, Get get) {
+    while (i + 1 < n && get(imgs[i + 1]) <= v) ++i;
+    return i;
+}
+
+// image of a flat-grid item: one search per wave (uniform), then each lane
+// steps forward past the image boundaries inside the wave's 64 items
+template <typename Get>
+__device__ __forceinline__ int batch_find_wave(const BatchImage* imgs, int n, int v, Get get) {
+    const int v0 = __builtin_amdgcn_readfirstlane(v);
+    const int i0 = batch_find(imgs, n, v0, get);
+    return batch_advance(imgs, n, i0, v, get);
+}
+
+// contiguous share [begin, end) of `total` items for worker w of nw
+__device__ __forceinline__ void batch_share(int w, int nw, int total, int& begin, int& end) {
+    begin = (int)((int64_t)total * w / nw);
+    end = (int)((int64_t)total * (w + 1) / nw);
+}
+
+// Persistent tile passes: workgroup b takes a contiguous run of tiles (no
+// shared counter: tiles are uniform work, and same-address device atomics
+// from every workgroup would serialise), so neighbouring tiles and their
+// halo rows are handled by the same workgroup.
 template <int T>
 __global__ void __launch_bounds__(kWGThreads)
-k_hyst_local_batch(const BatchImage* imgs, const BatchDev* hdr, uint32_t* counter) {
+k_hyst_local_batch(const BatchImage* imgs, const BatchDev* hdr) {
     __shared__ LocalSmem<T> sm;
-    __shared__ int task_s;
-    const int n = hdr->n, total = hdr->total_tiles;
+    const int n = hdr->n;
     char* ws = hdr->ws;
-    for (int pass = 0; pass <= total; ++pass) {  // each pass claims a new tile
-        if (threadIdx.x == 0) task_s = (int)atomicAdd(counter, 1u);
-        __syncthreads();
-        const int task = task_s;
-        if (task >= total) break;
-        const int i = batch_find(imgs, n, task, [](const BatchImage& m) { return m.tile_base; });
+    int begin, end;
+    batch_share(blockIdx.x, gridDim.x, hdr->total_tiles, begin, end);
+    const auto base = [](const BatchImage& m) { return m.tile_base; };
+    int i = batch_find(imgs, n, begin, base);
+    for (int task = begin; task < end; ++task) {
+        i = batch_advance(imgs, n, i, task, base);
         const BatchImage& im = imgs[i];
         const int vec16 = ((uintptr_t)im.edges % 16 == 0) && (im.epitch % 16 == 0);
         local_tile<T>(batch_args(im, ws), task - im.tile_base, im.tiles_x, vec16, sm);
-        __syncthreads();  // LDS and task_s are reused by the next tile
+        __syncthreads();  // LDS is reused by the next tile
     }
 }
 
 template <int T>
 __global__ void __launch_bounds__(kWGThreads) k_hyst_merge_batch(const BatchImage* imgs, const BatchDev* hdr) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = batch_find_wave(imgs, hdr->n, min(g, hdr->total_merge - 1),
+                                  [](const BatchImage& m) { return m.merge_base; });
     if (g >= hdr->total_merge) return;
-    const int i = batch_find(imgs, hdr->n, g, [](const BatchImage& m) { return m.merge_base; });
     const BatchImage& im = imgs[i];
     const int local = g - im.merge_base;
     const int tile = local / (T + kHystCols);
@@ -551,42 +578,42 @@ __global__ void __launch_bounds__(kWGThreads) k_hyst_merge_batch(const BatchImag
 
 __global__ void __launch_bounds__(kWGThreads) k_hyst_flags_batch(const BatchImage* imgs, const BatchDev* hdr) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = batch_find_wave(imgs, hdr->n, min(g, hdr->total_slots - 1),
+                                  [](const BatchImage& m) { return m.slot_base; });
     if (g >= hdr->total_slots) return;
-    const int i = batch_find(imgs, hdr->n, g, [](const BatchImage& m) { return m.slot_base; });
     flags_one(batch_args(imgs[i], hdr->ws), g - imgs[i].slot_base);
 }
 
 template <int T>
 __global__ void __launch_bounds__(kWGThreads)
-k_hyst_resolve_batch(const BatchImage* imgs, const BatchDev* hdr, uint32_t* counter) {
+k_hyst_resolve_batch(const BatchImage* imgs, const BatchDev* hdr) {
     __shared__ uint8_t res[kWGThreads];
-    __shared__ int task_s;
-    const int n = hdr->n, total = hdr->total_tiles;
+    const int n = hdr->n;
     char* ws = hdr->ws;
-    for (int pass = 0; pass <= total; ++pass) {  // each pass claims a new tile
-        if (threadIdx.x == 0) task_s = (int)atomicAdd(counter, 1u);
-        __syncthreads();
-        const int task = task_s;
-        if (task >= total) break;
-        const int i = batch_find(imgs, n, task, [](const BatchImage& m) { return m.tile_base; });
+    int begin, end;
+    batch_share(blockIdx.x, gridDim.x, hdr->total_tiles, begin, end);
+    const auto base = [](const BatchImage& m) { return m.tile_base; };
+    int i = batch_find(imgs, n, begin, base);
+    for (int task = begin; task < end; ++task) {
+        i = batch_advance(imgs, n, i, task, base);
         const BatchImage& im = imgs[i];
         const int vec16 = ((uintptr_t)im.edges % 16 == 0) && (im.epitch % 16 == 0);
         resolve_tile<T>(batch_args(im, ws), task - im.tile_base, im.tiles_x, vec16, res);
-        __syncthreads();  // res and task_s are reused by the next tile
+        __syncthreads();  // res is reused by the next tile
     }
 }
 
 }  // namespace
 
-hipError_t launch_hyst_batch(const BatchImage* imgs, const BatchDev* hdr, uint32_t* counters,
-                             int total_merge, int total_slots, int nwg, hipStream_t s) {
+hipError_t launch_hyst_batch(const BatchImage* imgs, const BatchDev* hdr, int total_merge,
+                             int total_slots, int nwg, hipStream_t s) {
     constexpr int T = 64;
-    hipLaunchKernelGGL(k_hyst_local_batch<T>, dim3(nwg), dim3(kWGThreads), 0, s, imgs, hdr, counters);
+    hipLaunchKernelGGL(k_hyst_local_batch<T>, dim3(nwg), dim3(kWGThreads), 0, s, imgs, hdr);
     hipLaunchKernelGGL(k_hyst_merge_batch<T>, dim3(ceil_div(max(total_merge, 1), kWGThreads)),
                        dim3(kWGThreads), 0, s, imgs, hdr);
     hipLaunchKernelGGL(k_hyst_flags_batch, dim3(ceil_div(max(total_slots, 1), kWGThreads)),
                        dim3(kWGThreads), 0, s, imgs, hdr);
-    hipLaunchKernelGGL(k_hyst_resolve_batch<T>, dim3(nwg), dim3(kWGThreads), 0, s, imgs, hdr, counters + 1);
+    hipLaunchKernelGGL(k_hyst_resolve_batch<T>, dim3(nwg), dim3(kWGThreads), 0, s, imgs, hdr);
     return hipGetLastError();
 }
 

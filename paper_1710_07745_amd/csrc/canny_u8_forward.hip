@@ -326,26 +326,28 @@ k_u8_forward(U8FwdArgs a, int strips_x, int nwaves, int fast_ok) {
     else walk<R, true>(a, X0, Y0, lane, fast_ok);
 }
 
-// Persistent batch forward: each wave claims (image, strip, row block) tasks
-// from a device counter until every image of the batch is covered.
+// Persistent batch forward: each wave takes a contiguous run of (image,
+// strip, row block) tasks.
 template <int R>
 __global__ void __launch_bounds__(kWGThreads)
-k_u8_forward_batch(const BatchImage* imgs, const BatchDev* hdr, uint32_t* counter) {
+k_u8_forward_batch(const BatchImage* imgs, const BatchDev* hdr) {
     const int lane = threadIdx.x & (kWave - 1);
     const int n = hdr->n, total = hdr->total_fwd;
     char* ws = hdr->ws;
-    // every pass claims a new task, so total + 1 passes always end the loop
-    for (int pass = 0; pass <= total; ++pass) {
-        uint32_t task = 0;
-        if (lane == 0) task = atomicAdd(counter, 1u);
-        const int tk = __builtin_amdgcn_readfirstlane((int)task);
-        if (tk >= total) break;
-        int lo = 0, hi = n - 1;  // last image whose first task is <= tk
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (imgs[mid].fwd_base <= tk) lo = mid;
-            else hi = mid - 1;
-        }
+    // wave w of nw takes the contiguous task run [begin, end): tasks are
+    // uniform strips, and no shared counter is touched
+    const int nw = gridDim.x * kWavesPerWG;
+    const int w = blockIdx.x * kWavesPerWG + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int begin = (int)((int64_t)total * w / nw);
+    const int end = (int)((int64_t)total * (w + 1) / nw);
+    int lo = 0, hi = n - 1;  // last image whose first task is <= begin
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (imgs[mid].fwd_base <= begin) lo = mid;
+        else hi = mid - 1;
+    }
+    for (int tk = begin; tk < end; ++tk) {
+        while (lo + 1 < n && imgs[lo + 1].fwd_base <= tk) ++lo;
         const BatchImage& im = imgs[lo];
         U8FwdArgs a;
         a.in = im.in;
@@ -370,13 +372,13 @@ k_u8_forward_batch(const BatchImage* imgs, const BatchDev* hdr, uint32_t* counte
 
 }  // namespace
 
-hipError_t launch_u8_forward_batch(const BatchImage* imgs, const BatchDev* hdr, uint32_t* counter,
-                                   int rows_per_wave, int nwg, hipStream_t s) {
-    switch (rows_per_wave) {
-        case 16: hipLaunchKernelGGL(k_u8_forward_batch<16>, dim3(nwg), dim3(kWGThreads), 0, s, imgs, hdr, counter); break;
-        case 48: hipLaunchKernelGGL(k_u8_forward_batch<48>, dim3(nwg), dim3(kWGThreads), 0, s, imgs, hdr, counter); break;
-        case 64: hipLaunchKernelGGL(k_u8_forward_batch<64>, dim3(nwg), dim3(kWGThreads), 0, s, imgs, hdr, counter); break;
-        default: hipLaunchKernelGGL(k_u8_forward_batch<32>, dim3(nwg), dim3(kWGThreads), 0, s, imgs, hdr, counter); break;
+hipError_t launch_u8_forward_batch(const BatchImage* imgs, const BatchDev* hdr, int rows, int nwg,
+                                   hipStream_t s) {
+    switch (rows) {
+        case 16: hipLaunchKernelGGL(k_u8_forward_batch<16>, dim3(nwg), dim3(kWGThreads), 0, s, imgs, hdr); break;
+        case 48: hipLaunchKernelGGL(k_u8_forward_batch<48>, dim3(nwg), dim3(kWGThreads), 0, s, imgs, hdr); break;
+        case 64: hipLaunchKernelGGL(k_u8_forward_batch<64>, dim3(nwg), dim3(kWGThreads), 0, s, imgs, hdr); break;
+        default: hipLaunchKernelGGL(k_u8_forward_batch<32>, dim3(nwg), dim3(kWGThreads), 0, s, imgs, hdr); break;
     }
     return hipGetLastError();
 }
