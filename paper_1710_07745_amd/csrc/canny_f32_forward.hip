@@ -479,12 +479,12 @@ void launch_walk(const F32FwdArgs& a, int fast_ok, hipStream_t s) {
 
 // Rows per wave: a wave walks its strip serially, so long strips suit large
 // images (halo rows amortised) and short ones small images (more waves in
-// flight).  32 unless that leaves fewer than 1024 waves (one per SIMD).
+// flight).  36 unless that leaves fewer than 1024 waves (one per SIMD).
 template <int R, bool SIGNED>
 void launch_walk_sized(const F32FwdArgs& a, int fast_ok, hipStream_t s) {
     const int strips_x = ceil_div(a.W, WalkShape<R>::SC);
-    if ((int64_t)strips_x * ceil_div(a.H, 32) >= 1024)
-        launch_walk<R, 32, SIGNED>(a, fast_ok, s);
+    if ((int64_t)strips_x * ceil_div(a.H, 36) >= 1024)
+        launch_walk<R, 36, SIGNED>(a, fast_ok, s);
     else
         launch_walk<R, 8, SIGNED>(a, fast_ok, s);
 }
