@@ -18,13 +18,18 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I" + os.path.join(HERE, "..", "include"),
 ]
-# per-file extras: the float walk unrolls its row loop completely (sliding
-# windows become register renaming), which needs a higher unroll limit
+# per-file extras: the strip walks unroll their row loops completely
+# (sliding windows become register renaming), which needs a higher unroll
+# limit; the differentiable kernels are split into radius groups so that
+# those large compiles run in parallel
 # the float kernels' inputs are finite by contract, so min/max need no NaN
 # canonicalisation (-fno-honor-nans)
+UNROLL = ["-mllvm", "-pragma-unroll-threshold=1000000"]
 EXTRA = {
-    "canny_f32_forward.hip": ["-mllvm", "-pragma-unroll-threshold=1000000", "-fno-honor-nans"],
+    "canny_f32_forward.hip": UNROLL + ["-fno-honor-nans"],
+    "canny_u8_forward.hip": UNROLL,
 }
+EXTRA.update({f"canny_mag_g{g}.hip": UNROLL + ["-fno-honor-nans"] for g in range(1, 7)})
 
 
 def _compile(src: str) -> str:
@@ -38,7 +43,9 @@ def _compile(src: str) -> str:
 
 def build(jobs: int | None = None) -> str:
     os.makedirs(OBJ, exist_ok=True)
-    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+    # the long (unrolled) compiles first, so they overlap the short ones
+    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")),
+                  key=lambda f: (os.path.basename(f) not in EXTRA, f))
     jobs = jobs or min(8, os.cpu_count() or 4, len(srcs))
     with cf.ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(_compile, srcs))
