@@ -209,11 +209,24 @@ int canny_f32(const float* in, int64_t in_pitch, int H, int W, float sigma, int 
     f.cpitch = class_pitch(W);
     f.mag = mag_out;
     f.max_out = max_out;
+    // With the signed map and nothing but edges (and the max) asked for, the
+    // hysteresis pass classifies straight from the signed map: no class map.
+    const bool fused = f.smag && !class2 && !mag_out && edges;
+    f.skip_classify = fused ? 1 : 0;
     hipError_t e = launch_f32_forward(f, s);
     if (e != hipSuccess || !edges) return status_of(e);
     HystArgs h;
     h.cls = f.cls;
     h.cpitch = f.cpitch;
+    if (fused) {
+        h.smag = f.smag;
+        h.spitch = f.spitch;
+        h.maxbits = f.maxbits;
+        h.low = low;
+        h.high = high;
+        h.relative = f.relative;
+        h.max_out = max_out;
+    }
     h.H = H;
     h.W = W;
     h.edges = edges;

@@ -507,7 +507,7 @@ hipError_t launch_radius(const F32FwdArgs& a, hipStream_t s) {
         StageTimer t(CANNY_STAGE_F32_WALK, s);
         launch_walk_sized<R, true>(b, fast_ok, s);
     }
-    {
+    if (!a.skip_classify) {
         StageTimer t(CANNY_STAGE_F32_CLASSIFY, s);
         hipLaunchKernelGGL(k_f32_classify, dim3(rows_grid(a.H)), dim3(kRowThreads), 0, s, b);
     }

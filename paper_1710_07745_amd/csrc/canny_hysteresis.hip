@@ -151,23 +151,51 @@ struct TileLabel {
 // afterwards L[r*64 + s] is the root (smallest index) of the component of
 // the run that starts at column s of row r; only run starts carry entries.
 // cm holds the 64-bit candidate mask of every tile row.
+// Class codes (2 bits per pixel, pixel k at bits 2k) of 16 pixels of the
+// signed strength map: kept (value > 0) and > hi -> 2, kept and >= lo -> 1.
+__device__ __forceinline__ uint32_t codes_from_signed(const float* row, int nquads, float lo, float hi) {
+    uint32_t codes = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (q >= nquads) break;
+        const float4 v = reinterpret_cast<const float4*>(row)[q];
+        const float e[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t c = e[k] > 0.0f ? (e[k] > hi ? 2u : (e[k] >= lo ? 1u : 0u)) : 0u;
+            codes |= c << (2 * (4 * q + k));
+        }
+    }
+    return codes;
+}
+
 template <int T>
-__device__ __forceinline__ TileLabel<T> tile_label(const uint8_t* cls, int64_t cpitch, int W,
-                                                   const TileGeom& g, int* L, uint64_t* cm) {
+__device__ __forceinline__ TileLabel<T> tile_label(const HystArgs& a, const TileGeom& g, int* L,
+                                                   uint64_t* cm) {
     using TL = Tile<T>;
     static_assert(TL::kPPT == 16, "row masks assume 16-pixel segments");
+    const int W = a.W;
     const int t = threadIdx.x;
     const int r = t / TL::kTPR;
     const int seg = t % TL::kTPR;
     const int cb = seg * TL::kPPT;
     uint32_t codes = 0;
     if (r < g.th) {
-        const uint8_t* row = cls + (int64_t)(g.Y0 + r) * cpitch + ((g.X0 + cb) >> 2);
-        const int avail = (int)(cpitch - ((g.X0 + cb) >> 2));  // bytes left in the row
-        if (avail >= 4) {
-            codes = *reinterpret_cast<const uint32_t*>(row);
+        if (a.smag) {
+            const float mx = __uint_as_float(*a.maxbits);
+            const float lo = a.relative ? a.low * mx : a.low;
+            const float hi = a.relative ? a.high * mx : a.high;
+            // whole quads that the row pitch holds from this segment on
+            const int nq = (int)min((int64_t)4, max((int64_t)0, (a.spitch - (g.X0 + cb)) >> 2));
+            codes = codes_from_signed(a.smag + (int64_t)(g.Y0 + r) * a.spitch + g.X0 + cb, nq, lo, hi);
         } else {
-            for (int k = 0; k < avail; ++k) codes |= (uint32_t)row[k] << (8 * k);
+            const uint8_t* row = a.cls + (int64_t)(g.Y0 + r) * a.cpitch + ((g.X0 + cb) >> 2);
+            const int avail = (int)(a.cpitch - ((g.X0 + cb) >> 2));  // bytes left in the row
+            if (avail >= 4) {
+                codes = *reinterpret_cast<const uint32_t*>(row);
+            } else {
+                for (int k = 0; k < avail; ++k) codes |= (uint32_t)row[k] << (8 * k);
+            }
         }
         // pixels past the image edge are not candidates
         const int valid = min(max(W - (g.X0 + cb), 0), TL::kPPT);
@@ -306,7 +334,8 @@ __device__ __forceinline__ void local_tile(const HystArgs& a, int tile, int tile
     const TileGeom g = tile_geom<T>(tile, tiles_x, a.H, a.W);
     const int t = threadIdx.x;
     for (int s = t; s < TL::kPerim; s += kWGThreads) bl[s] = -1;  // "no candidate"
-    const TileLabel<T> st = tile_label<T>(a.cls, a.cpitch, a.W, g, L, sm.cm);
+    if (a.max_out && tile == 0 && t == 0) *a.max_out = __uint_as_float(*a.maxbits);
+    const TileLabel<T> st = tile_label<T>(a, g, L, sm.cm);
     const int r = t / TL::kTPR;
     const int cb = (t % TL::kTPR) * TL::kPPT;
     const int me = r * kHystCols;

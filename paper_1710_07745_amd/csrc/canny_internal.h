@@ -80,6 +80,16 @@ int u8_forward_supported_rows(int rows);
 struct HystArgs {
     const uint8_t* cls;
     int64_t cpitch;
+    // Alternative source (float path, cls unused): the signed strength map of
+    // the float walk, classified on the fly with the thresholds below (scaled
+    // by the largest strength in maxbits when relative); the largest
+    // strength is also written to max_out when that is non-NULL.
+    const float* smag = nullptr;
+    int64_t spitch = 0;
+    const uint32_t* maxbits = nullptr;
+    float low = 0.0f, high = 0.0f;
+    int relative = 0;
+    float* max_out = nullptr;
     int H, W;
     uint8_t* edges;
     int64_t epitch;
@@ -109,6 +119,7 @@ struct F32FwdArgs {
     int64_t cpitch;
     float* mag;       // optional
     float* max_out;   // optional
+    int skip_classify;  // signed path only: the hysteresis pass classifies instead
 };
 // stage timing (canny_timing.hip): timing_begin returns a slot (or -1 when
 // timing is off or the stage's pool is full) that timing_end closes

@@ -170,3 +170,23 @@ def test_float_stage_timing(canny):
         assert t.read("u8_forward") == (0.0, 0)
     nb = (X.shape[1] + 3) // 4  # class bytes of a row (padding past them is unspecified)
     assert torch.equal(e, ref_e) and torch.equal(c[:, :nb], ref_c[:, :nb])
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (5, 7), (63, 65), (200, 333), (1001, 2049), (4096, 4096)])
+def test_float_edges_only_path(canny, shape):
+    """Edges alone (no class map or strength requested) take the path where
+    the hysteresis pass classifies from the signed strength map; it must give
+    the same edges, bit for bit, as the path through an explicit class map,
+    and those equal BFS on that class map."""
+    H, W = shape
+    X = workloads.natural_u8(H, W, seed=77 + H).astype(np.float32)
+    dev = torch.from_numpy(X).cuda()
+    e_fused, mx = canny.canny_f32(dev, return_max=True)
+    e_cls, cls = canny.canny_f32(dev, return_classes=True)
+    torch.cuda.synchronize()
+    assert torch.equal(e_fused, e_cls)
+    be, _ = oracle.hysteresis(unpack_classes(cls.cpu().numpy(), H, W))
+    assert np.array_equal(e_fused.cpu().numpy(), be)
+    if H * W <= 1 << 20:
+        _, _, _, omx = oracle.classify_f32(X, 1.4, 3)
+        assert abs(float(mx.cpu()[0]) - omx) <= TOL * omx
