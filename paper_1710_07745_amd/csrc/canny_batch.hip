@@ -97,6 +97,7 @@ void layout(canny_batch_plan& p, const int32_t* H, const int32_t* W) {
         m.blab_off = (int64_t)off + (reinterpret_cast<char*>(h.blab) - base);
         m.parent_off = (int64_t)off + (reinterpret_cast<char*>(h.parent) - base);
         m.flag_off = (int64_t)off + (reinterpret_cast<char*>(h.flag) - base);
+        m.pmask_off = (int64_t)off + (reinterpret_cast<char*>(h.pmask) - base);
         off += al256(hyst_workspace_bytes(m.H, m.W, kT));
         m.tiles_x = ceil_div(m.W, kHystCols);
         m.tiles_y = ceil_div(m.H, kT);

@@ -50,8 +50,9 @@ struct Tile {
 };
 
 // find with path halving (each visited pointer is replaced by its grandparent,
-// an ancestor); used only while unions are running, before the pointer-jumping
-// flatten, so a halving store can never overwrite a finished root pointer
+// an ancestor); used only while unions are running, before the root walks
+// that follow them, so a halving store can never overwrite a finished root
+// pointer
 __device__ __forceinline__ int lds_find_halve(volatile int* L, int x) {
     for (int steps = x; steps >= 0; --steps) {  // pointers decrease: at most x + 1 hops
         const int p = L[x];
@@ -363,17 +364,22 @@ __device__ __forceinline__ void local_tile(const HystArgs& a, int tile, int tile
         }
     }
     __syncthreads();
+    bool pending = false;
     if (r < g.th) {
         Seg16 out;
         for (uint32_t b = st.cand; b; b &= b - 1) {
             const int k = __ffs(b) - 1;
             const int v = L[L[me + run_start(st.S, cb + k)] & kRootMask];
             const uint32_t br = (uint32_t)v >> kBrepShift;
+            pending |= br != 0;
             out.set(k, br ? br : ((v & kStrongBit) ? 255u : 0u));
         }
         const int valid = min(a.W - (g.X0 + cb), TL::kPPT);
         if (valid > 0) store_seg(a.edges + (int64_t)(g.Y0 + r) * a.epitch + g.X0 + cb, out, valid, vec16);
     }
+    // one bit per thread segment with pending codes, one word per wave
+    const uint64_t pm = __ballot(pending);
+    if ((t & (kWave - 1)) == 0) a.pmask[(int64_t)g.tile * (kWGThreads / kWave) + t / kWave] = pm;
     const int base = g.tile * TL::kPerim;
     for (int s = t; s < TL::kPerim; s += kWGThreads) a.blab[base + s] = bl[s];
 }
@@ -452,17 +458,25 @@ __global__ void __launch_bounds__(kWGThreads) k_hyst_flags(HystArgs a, int nslot
 }
 
 // Pass 4 on one tile: pending codes 1..252 become 255 / 0 by the global flag
-// of their component; everything else is already final.  The workgroup first
-// resolves every border pixel index once (res: LDS, 252 entries), so each
-// pending pixel costs one LDS read; a tile without border components is left
-// untouched.
+// of their component; everything else is already final.  Only the thread
+// segments the local pass marked in pmask are read and rewritten (a tile
+// without any is skipped); the workgroup resolves every border pixel index
+// once (res: LDS, 252 entries), so each pending pixel costs one LDS read.
 template <int T>
 __device__ __forceinline__ void resolve_tile(const HystArgs& a, int tile, int tiles_x, int vec16,
                                              uint8_t* res) {
     using TL = Tile<T>;
     static_assert(kWGThreads >= 3 * kHystCols + T - 4, "one thread per border pixel index");
-    const TileGeom g = tile_geom<T>(tile, tiles_x, a.H, a.W);
     const int t = threadIdx.x;
+    // segments with pending codes (the local pass's masks; identical reads in
+    // every thread, so the early exit below is uniform)
+    const uint64_t* pmt = a.pmask + (int64_t)tile * (kWGThreads / kWave);
+    uint64_t any_pm = 0;
+#pragma unroll
+    for (int w = 0; w < kWGThreads / kWave; ++w) any_pm |= pmt[w];
+    if (!any_pm) return;
+    const bool mine = (pmt[t / kWave] >> (t & (kWave - 1))) & 1ull;
+    const TileGeom g = tile_geom<T>(tile, tiles_x, a.H, a.W);
     const int r = t / TL::kTPR;
     const int cb = (t % TL::kTPR) * TL::kPPT;
     const int valid = r < g.th ? min(a.W - (g.X0 + cb), TL::kPPT) : 0;
@@ -470,30 +484,29 @@ __device__ __forceinline__ void resolve_tile(const HystArgs& a, int tile, int ti
     // the segment's bytes are read first so that their latency overlaps the
     // lookups below
     Seg16 out;
-    if (vec16 && valid == TL::kPPT) {
-        const uint4 v = *reinterpret_cast<const uint4*>(dst);
-        out.lo = v.x | (uint64_t)v.y << 32;
-        out.hi = v.z | (uint64_t)v.w << 32;
-    } else {
-        for (int k = 0; k < valid; ++k) out.set(k, dst[k]);
+    if (mine) {
+        if (vec16 && valid == TL::kPPT) {
+            const uint4 v = *reinterpret_cast<const uint4*>(dst);
+            out.lo = v.x | (uint64_t)v.y << 32;
+            out.hi = v.z | (uint64_t)v.w << 32;
+        } else {
+            for (int k = 0; k < valid; ++k) out.set(k, dst[k]);
+        }
     }
     const int base = g.tile * TL::kPerim;
-    bool named = false;
     if (t < 2 * kHystCols + 2 * (T - 2)) {
         const int gid = a.blab[base + border_slot<T>(t)];
-        named = gid >= 0;
-        res[t] = named && a.flag[a.parent[gid]] ? 255 : 0;
+        res[t] = gid >= 0 && a.flag[a.parent[gid]] ? 255 : 0;
     }
-    if (!__syncthreads_or(named)) return;  // no border component: nothing pending
-    bool any = false;
+    __syncthreads();
+    if (!mine) return;
 #pragma unroll
     for (int k = 0; k < TL::kPPT; ++k) {
         const uint32_t e = out.get(k);
         if (e == 0 || e == 255) continue;  // final already (bytes past `valid` are 0)
         out.put(k, res[e - 1]);
-        any = true;
     }
-    if (any) store_seg(dst, out, valid, vec16);
+    store_seg(dst, out, valid, vec16);
 }
 
 template <int T>
@@ -532,6 +545,7 @@ __device__ __forceinline__ HystArgs batch_args(const BatchImage& im, char* ws) {
     a.blab = reinterpret_cast<int32_t*>(ws + im.blab_off);
     a.parent = reinterpret_cast<int32_t*>(ws + im.parent_off);
     a.flag = reinterpret_cast<int32_t*>(ws + im.flag_off);
+    a.pmask = reinterpret_cast<uint64_t*>(ws + im.pmask_off);
     return a;
 }
 
@@ -653,11 +667,13 @@ static int perim(int tile_rows) { return 2 * kHystCols + 2 * tile_rows; }
 static size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 // blab: int32 per border slot; parent, flag: int32 per tile pixel (sparsely
-// touched: only entries named by a border component)
+// touched: only entries named by a border component); pmask: one 64-bit word
+// per wave of a tile
 size_t hyst_workspace_bytes(int H, int W, int tile_rows) {
     const size_t ntiles = (size_t)ceil_div(W, kHystCols) * ceil_div(H, tile_rows);
     const size_t npx = ntiles * (size_t)kHystCols * tile_rows;
-    return al256(ntiles * perim(tile_rows) * 4) + 2 * al256(npx * 4);
+    return al256(ntiles * perim(tile_rows) * 4) + 2 * al256(npx * 4) +
+           al256(ntiles * (kWGThreads / kWave) * 8);
 }
 
 void hyst_carve(void* ws, int H, int W, int tile_rows, HystArgs& a) {
@@ -669,6 +685,8 @@ void hyst_carve(void* ws, int H, int W, int tile_rows, HystArgs& a) {
     a.parent = reinterpret_cast<int32_t*>(p);
     p += al256(npx * 4);
     a.flag = reinterpret_cast<int32_t*>(p);
+    p += al256(npx * 4);
+    a.pmask = reinterpret_cast<uint64_t*>(p);
 }
 
 hipError_t launch_hysteresis(const HystArgs& a, int tile_rows, hipStream_t s) {

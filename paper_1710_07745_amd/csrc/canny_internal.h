@@ -96,6 +96,7 @@ struct HystArgs {
     int32_t* blab;    // [ntiles * perim] global component name of each border pixel
     int32_t* parent;  // [ntiles * 64T] union-find forest over component names (sparse)
     int32_t* flag;    // [ntiles * 64T] strong flags (sparse)
+    uint64_t* pmask;  // [ntiles * 4] per wave of a tile: which thread segments hold pending codes
 };
 int hyst_tile_rows_default();
 size_t hyst_workspace_bytes(int H, int W, int tile_rows);
@@ -147,7 +148,7 @@ struct BatchImage {
     int64_t epitch;
     int H, W;
     int64_t cpitch;
-    int64_t cls_off, blab_off, parent_off, flag_off;  // bytes into the workspace
+    int64_t cls_off, blab_off, parent_off, flag_off, pmask_off;  // bytes into the workspace
     int fwd_strips_x, fwd_base;  // forward wave tasks before this image
     int tiles_x, tiles_y, tile_base;
     int merge_base, slot_base;
