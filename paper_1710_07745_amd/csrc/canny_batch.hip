@@ -233,9 +233,9 @@ hipError_t autotune(canny_batch_plan& p) {
                 e = upload_sync(p);
                 float t = 1e30f;
                 for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) {
-                    hipEventRecord(t0, nullptr);
+                    (void)hipEventRecord(t0, nullptr);
                     e = enqueue(p, nullptr);
-                    hipEventRecord(t1, nullptr);
+                    (void)hipEventRecord(t1, nullptr);
                     if (e == hipSuccess) e = hipEventSynchronize(t1);
                     float ms = 0.0f;
                     if (e == hipSuccess && rep > 0 && hipEventElapsedTime(&ms, t0, t1) == hipSuccess)
@@ -254,29 +254,29 @@ hipError_t autotune(canny_batch_plan& p) {
             tune_store(key, best_rows, best_wgs);
         }
     }
-    hipDeviceSynchronize();
+    (void)hipDeviceSynchronize();
     for (BatchImage& m : p.imgs) {
         m.in = nullptr;
         m.edges = nullptr;
     }
     p.hdr.ws = nullptr;
-    if (t0) hipEventDestroy(t0);
-    if (t1) hipEventDestroy(t1);
-    if (in) hipFree(in);
-    if (out) hipFree(out);
-    if (ws) hipFree(ws);
+    if (t0) (void)hipEventDestroy(t0);
+    if (t1) (void)hipEventDestroy(t1);
+    if (in) (void)hipFree(in);
+    if (out) (void)hipFree(out);
+    if (ws) (void)hipFree(ws);
     return e;
 }
 
 void release(canny_batch_plan* p) {
     if (!p) return;
-    if (p->exec) hipGraphExecDestroy(p->exec);
-    if (p->graph) hipGraphDestroy(p->graph);
-    if (p->uploaded) hipEventDestroy(p->uploaded);
-    if (p->d_imgs) hipFree(p->d_imgs);
-    if (p->d_hdr) hipFree(p->d_hdr);
-    if (p->h_stage) hipHostFree(p->h_stage);
-    if (p->h_stage_hdr) hipHostFree(p->h_stage_hdr);
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->uploaded) (void)hipEventDestroy(p->uploaded);
+    if (p->d_imgs) (void)hipFree(p->d_imgs);
+    if (p->d_hdr) (void)hipFree(p->d_hdr);
+    if (p->h_stage) (void)hipHostFree(p->h_stage);
+    if (p->h_stage_hdr) (void)hipHostFree(p->h_stage_hdr);
     delete p;
 }
 
@@ -340,7 +340,7 @@ int canny_batch_plan_create(int n, const int32_t* H, const int32_t* W, int32_t l
         if (e == hipSuccess) e = le;
     }
     if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
-    if (cs) hipStreamDestroy(cs);
+    if (cs) (void)hipStreamDestroy(cs);
     if (e != hipSuccess) {
         release(p);
         return CANNY_ERR_HIP;
@@ -393,7 +393,7 @@ int canny_batch(canny_batch_plan* p, const uint8_t* const* in, const int64_t* in
 
 void canny_batch_plan_destroy(canny_batch_plan* p) {
     if (!p) return;
-    hipDeviceSynchronize();
+    (void)hipDeviceSynchronize();
     release(p);
 }
 

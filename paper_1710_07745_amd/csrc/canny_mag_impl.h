@@ -502,7 +502,7 @@ k_mag_bwd_b(const float* I, const float* sigma, const float* dB, int N, int H, i
     }
 }
 
-__global__ void __launch_bounds__(kWGThreads)
+__global__ void __launch_bounds__(kWGThreads) __attribute__((unused))
 k_mag_reduce(const float* partial, int per_img, float* dsigma) {
     __shared__ double s[kWGThreads];
     const int n = blockIdx.x;
