@@ -350,9 +350,9 @@ constexpr int kRowBatch = 8;  // rows a thread reads per batch (loads in flight)
 
 // Input min and max, one (min, max) pair per workgroup written to
 // a.range[blockIdx.x] (no atomics: the walk reduces the pairs itself).
-// Workgroup b owns rows b, b + gridDim.x, ...; a thread takes quad columns
-// q = threadIdx.x + 256 j of those rows, kRowBatch rows per batch so that
-// that many loads are in flight.  Also clears the largest-strength word the
+// Workgroup b owns a contiguous run of ceil(H / gridDim.x) rows; a thread
+// takes quad columns q = threadIdx.x + 256 j of those rows, kRowBatch rows
+// per batch so that that many loads are in flight.  Also clears the largest-strength word the
 // walk reduces into, which is safe because the walk is launched after this
 // kernel.
 __global__ void __launch_bounds__(kRowThreads)
@@ -360,9 +360,11 @@ k_f32_minmax(F32FwdArgs a, int quads_ok) {
     if (blockIdx.x == 0 && threadIdx.x == 0) *a.maxbits = 0u;
     float lo = 3.402823466e38f, hi = -3.402823466e38f;
     const int W = a.W;
-    const int nrows = (a.H - (int)blockIdx.x + (int)gridDim.x - 1) / (int)gridDim.x;
-    const int64_t rstride = (int64_t)gridDim.x * a.pitch;
-    const float* base = a.in + (int64_t)blockIdx.x * a.pitch;
+    const int chunk = (a.H + (int)gridDim.x - 1) / (int)gridDim.x;
+    const int y0 = (int)blockIdx.x * chunk;
+    const int nrows = max(0, min(chunk, a.H - y0));
+    const int64_t rstride = a.pitch;
+    const float* base = a.in + (int64_t)y0 * a.pitch;
     if (quads_ok) {
         const int nq = W >> 2;
         for (int q = threadIdx.x; q < nq; q += kRowThreads) {
