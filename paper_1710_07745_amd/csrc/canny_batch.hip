@@ -3,12 +3,13 @@
 //
 // A plan fixes the sizes and thresholds and lays out one workspace region per
 // image (class map + hysteresis state).  Every phase of the detector runs as
-// ONE launch over all images: the forward and the two per-tile hysteresis
-// passes are persistent kernels: each wave (forward) or workgroup (tiles)
-// takes a contiguous share of the batch's work items, which are uniform
-// strips / tiles, so large and small images interleave freely and no shared
-// counter is touched; the two per-border-pixel passes are flat grids over
-// all images.  The launches are recorded once into a HIP graph
+// ONE launch over all images: the forward and the local hysteresis pass are
+// persistent kernels: each wave (forward) or workgroup (tiles) takes a
+// contiguous share of the batch's work items, which are uniform strips /
+// tiles, so large and small images interleave freely and no shared counter
+// is touched; the two per-border-pixel passes and the resolve pass (one
+// workgroup per tile, most of which exit at once) are flat grids over all
+// images.  The launches are recorded once into a HIP graph
 //     forward -> local -> merge -> flags -> resolve
 // whose kernels read a device descriptor table; a call uploads the table
 // (the caller's image pointers and workspace) and replays the graph, so new
@@ -133,7 +134,8 @@ hipError_t enqueue(const canny_batch_plan& p, hipStream_t s) {
     const int nwg = p.cus * p.wgs_per_cu;
     hipError_t e = launch_u8_forward_batch(p.d_imgs, p.d_hdr, p.fwd_rows, nwg, s);
     if (e != hipSuccess) return e;
-    return launch_hyst_batch(p.d_imgs, p.d_hdr, p.hdr.total_merge, p.hdr.total_slots, nwg, s);
+    return launch_hyst_batch(p.d_imgs, p.d_hdr, p.hdr.total_tiles, p.hdr.total_merge,
+                             p.hdr.total_slots, nwg, s);
 }
 
 // synchronous upload of the table (plan creation and tuning only)
