@@ -157,8 +157,8 @@ int canny_f32(const float* in, int64_t in_pitch, int H, int W, float sigma, int 
  *   edges_pitch HOST arrays of n pitches (bytes).  Returns
  *   CANNY_ERR_INVALID on NULL or pitch < W.  Calls with the same plan must
  *   not overlap (the plan's pointer table and graph are shared).
- * canny_batch_plan_info: host copies of the chosen forward rows-per-wave,
- *   hysteresis tile height and persistent workgroups per CU.
+ * canny_batch_plan_info: host copies of the chosen forward tile height
+ *   (output rows per wave) and of the hysteresis tile height.
  */
 typedef struct canny_batch_plan canny_batch_plan;
 int canny_batch_plan_create(int n, const int32_t* H, const int32_t* W, int32_t low, int32_t high,
@@ -167,8 +167,7 @@ size_t canny_batch_workspace_bytes(const canny_batch_plan* plan);
 int canny_batch(canny_batch_plan* plan, const uint8_t* const* in, const int64_t* in_pitch,
                 uint8_t* const* edges, const int64_t* edges_pitch, void* ws, size_t ws_bytes,
                 void* stream);
-int canny_batch_plan_info(const canny_batch_plan* plan, int32_t* fwd_rows, int32_t* hyst_rows,
-                          int32_t* wgs_per_cu);
+int canny_batch_plan_info(const canny_batch_plan* plan, int32_t* fwd_rows, int32_t* hyst_rows);
 void canny_batch_plan_destroy(canny_batch_plan* plan);
 
 /* ---------------------------------------------------------------------

@@ -157,9 +157,9 @@ class BatchPlan:
         self._ws = None
 
     def info(self):
-        a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
-        check("canny_batch_plan_info", lib().canny_batch_plan_info(self._h, C.byref(a), C.byref(b), C.byref(c)))
-        return {"fwd_rows": a.value, "hyst_rows": b.value, "wgs_per_cu": c.value}
+        a, b = C.c_int32(), C.c_int32()
+        check("canny_batch_plan_info", lib().canny_batch_plan_info(self._h, C.byref(a), C.byref(b)))
+        return {"fwd_rows": a.value, "hyst_rows": b.value}
 
     def run(self, images: Sequence[torch.Tensor], edges: Optional[Sequence[torch.Tensor]] = None,
             workspace: Optional[torch.Tensor] = None) -> List[torch.Tensor]:

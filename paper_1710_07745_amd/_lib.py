@@ -39,7 +39,7 @@ SIGNATURES = {
     "canny_batch_plan_create": (C.c_int, [C.c_int, P, P, i32, i32, C.c_int, C.POINTER(P)]),
     "canny_batch_workspace_bytes": (sz, [P]),
     "canny_batch": (C.c_int, [P, P, P, P, P, P, sz, P]),
-    "canny_batch_plan_info": (C.c_int, [P, P, P, P]),
+    "canny_batch_plan_info": (C.c_int, [P, P, P]),
     "canny_batch_plan_destroy": (None, [P]),
     "canny_mag_forward": (C.c_int, [P, P, C.c_int, C.c_int, C.c_int, C.c_int, P, P]),
     "canny_mag_backward_workspace_bytes": (sz, [C.c_int, C.c_int, C.c_int, C.c_int]),

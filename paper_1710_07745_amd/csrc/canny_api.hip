@@ -74,7 +74,7 @@ const char* canny_status_string(int status) {
     }
 }
 
-int canny_abi_version(void) { return 1; }
+int canny_abi_version(void) { return 2; }
 
 int64_t canny_class_pitch(int W) { return class_pitch(W); }
 

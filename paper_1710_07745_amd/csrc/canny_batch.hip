@@ -15,11 +15,11 @@
 // (the caller's image pointers and workspace) and replays the graph, so new
 // buffers never need a new recording.
 //
-// Tuning: the forward's rows per wave and the persistent grid size (work-
-// groups per CU) are picked by timing every candidate on the plan's own
-// sizes with synthetic content, when asked; results are kept per process and,
-// if CANNY_TUNE_CACHE names a file, in that file as "key rows wgs_per_cu"
-// lines (key: arch, CU count, image count, hash of the sizes).
+// Tuning: the forward's tile height (output rows per wave) is picked by
+// timing every candidate on the plan's own sizes with synthetic content, when
+// asked; results are kept per process and, if CANNY_TUNE_CACHE names a file,
+// in that file as "key rows" lines (key: arch, CU count, image count, hash of
+// the sizes).
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -46,7 +46,6 @@ struct canny_batch_plan {
     int n = 0;
     int low = 0, high = 0;
     int fwd_rows = 32;
-    int wgs_per_cu = 4;
     int cus = 256;
     int device = 0;
     size_t ws_bytes = 0;
@@ -131,11 +130,10 @@ void set_fwd_rows(canny_batch_plan& p, int rows) {
 }
 
 hipError_t enqueue(const canny_batch_plan& p, hipStream_t s) {
-    const int nwg = p.cus * p.wgs_per_cu;
-    hipError_t e = launch_u8_forward_batch(p.d_imgs, p.d_hdr, p.fwd_rows, nwg, s);
+    hipError_t e = launch_u8_forward_batch(p.d_imgs, p.d_hdr, p.fwd_rows, p.hdr.total_fwd, s);
     if (e != hipSuccess) return e;
     return launch_hyst_batch(p.d_imgs, p.d_hdr, p.hdr.total_tiles, p.hdr.total_merge,
-                             p.hdr.total_slots, nwg, s);
+                             p.hdr.total_slots, s);
 }
 
 // synchronous upload of the table (plan creation and tuning only)
@@ -146,7 +144,7 @@ hipError_t upload_sync(canny_batch_plan& p) {
 }
 
 std::mutex g_tune_mu;
-std::map<std::string, std::pair<int, int>> g_tune_cache;
+std::map<std::string, int> g_tune_cache;
 
 std::string tune_key(const canny_batch_plan& p) {
     uint64_t h = 1469598103934665603ull;
@@ -159,7 +157,7 @@ std::string tune_key(const canny_batch_plan& p) {
     return buf;
 }
 
-bool tune_lookup(const std::string& key, int& rows, int& wgs) {
+bool tune_lookup(const std::string& key, int& rows) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune_cache.find(key);
     if (it == g_tune_cache.end()) {
@@ -168,34 +166,33 @@ bool tune_lookup(const std::string& key, int& rows, int& wgs) {
         FILE* f = std::fopen(path, "r");
         if (!f) return false;
         char k[128];
-        int r, w;
-        while (std::fscanf(f, "%127s %d %d", k, &r, &w) == 3) g_tune_cache[k] = {r, w};
+        int r;
+        while (std::fscanf(f, "%127s %d", k, &r) == 2)
+            if (u8_forward_supported_rows(r)) g_tune_cache[k] = r;
         std::fclose(f);
         it = g_tune_cache.find(key);
         if (it == g_tune_cache.end()) return false;
     }
-    rows = it->second.first;
-    wgs = it->second.second;
+    rows = it->second;
     return true;
 }
 
-void tune_store(const std::string& key, int rows, int wgs) {
+void tune_store(const std::string& key, int rows) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune_cache[key] = {rows, wgs};
+    g_tune_cache[key] = rows;
     if (const char* path = std::getenv("CANNY_TUNE_CACHE")) {
         if (FILE* f = std::fopen(path, "a")) {
-            std::fprintf(f, "%s %d %d\n", key.c_str(), rows, wgs);
+            std::fprintf(f, "%s %d\n", key.c_str(), rows);
             std::fclose(f);
         }
     }
 }
 
-// Time every (rows, wgs_per_cu) candidate on the plan's sizes; keep the best.
+// Time every tile height candidate on the plan's sizes; keep the best.
 hipError_t autotune(canny_batch_plan& p) {
     const std::string key = tune_key(p);
-    int rows, wgs;
-    if (tune_lookup(key, rows, wgs)) {
-        p.wgs_per_cu = wgs;
+    int rows;
+    if (tune_lookup(key, rows)) {
         set_fwd_rows(p, rows);
         return hipSuccess;
     }
@@ -224,36 +221,30 @@ hipError_t autotune(canny_batch_plan& p) {
         }
         p.hdr.ws = ws;
         float best = 1e30f;
-        int best_rows = 32, best_wgs = 4;
+        int best_rows = 32;
         const int cand_rows[] = {16, 32, 48, 64};
-        const int cand_wgs[] = {2, 4, 8};
         for (int r : cand_rows) {
-            for (int w : cand_wgs) {
-                if (e != hipSuccess) break;
-                set_fwd_rows(p, r);
-                p.wgs_per_cu = w;
-                e = upload_sync(p);
-                float t = 1e30f;
-                for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) {
-                    (void)hipEventRecord(t0, nullptr);
-                    e = enqueue(p, nullptr);
-                    (void)hipEventRecord(t1, nullptr);
-                    if (e == hipSuccess) e = hipEventSynchronize(t1);
-                    float ms = 0.0f;
-                    if (e == hipSuccess && rep > 0 && hipEventElapsedTime(&ms, t0, t1) == hipSuccess)
-                        t = ms < t ? ms : t;
-                }
-                if (t < best) {
-                    best = t;
-                    best_rows = r;
-                    best_wgs = w;
-                }
+            if (e != hipSuccess) break;
+            set_fwd_rows(p, r);
+            e = upload_sync(p);
+            float t = 1e30f;
+            for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) {
+                (void)hipEventRecord(t0, nullptr);
+                e = enqueue(p, nullptr);
+                (void)hipEventRecord(t1, nullptr);
+                if (e == hipSuccess) e = hipEventSynchronize(t1);
+                float ms = 0.0f;
+                if (e == hipSuccess && rep > 0 && hipEventElapsedTime(&ms, t0, t1) == hipSuccess)
+                    t = ms < t ? ms : t;
+            }
+            if (t < best) {
+                best = t;
+                best_rows = r;
             }
         }
         if (e == hipSuccess) {
-            p.wgs_per_cu = best_wgs;
             set_fwd_rows(p, best_rows);
-            tune_store(key, best_rows, best_wgs);
+            tune_store(key, best_rows);
         }
     }
     (void)hipDeviceSynchronize();
@@ -353,12 +344,10 @@ int canny_batch_plan_create(int n, const int32_t* H, const int32_t* W, int32_t l
 
 size_t canny_batch_workspace_bytes(const canny_batch_plan* p) { return p ? p->ws_bytes : 0; }
 
-int canny_batch_plan_info(const canny_batch_plan* p, int32_t* fwd_rows, int32_t* hyst_rows,
-                          int32_t* wgs_per_cu) {
+int canny_batch_plan_info(const canny_batch_plan* p, int32_t* fwd_rows, int32_t* hyst_rows) {
     if (!p) return CANNY_ERR_INVALID;
     if (fwd_rows) *fwd_rows = p->fwd_rows;
     if (hyst_rows) *hyst_rows = kT;
-    if (wgs_per_cu) *wgs_per_cu = p->wgs_per_cu;
     return CANNY_OK;
 }
 

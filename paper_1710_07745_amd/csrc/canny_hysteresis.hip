@@ -584,27 +584,18 @@ __device__ __forceinline__ void batch_share(int w, int nw, int total, int& begin
     end = (int)((int64_t)total * (w + 1) / nw);
 }
 
-// Persistent local pass: workgroup b takes a contiguous run of tiles (no
-// shared counter: tiles are uniform work, and same-address device atomics
-// from every workgroup would serialise), so neighbouring tiles are handled
-// by the same workgroup.
+// Local pass over the batch: one workgroup per tile, the image found by a
+// binary search over the tile bases.
 template <int T>
 __global__ void __launch_bounds__(kWGThreads)
 k_hyst_local_batch(const BatchImage* imgs, const BatchDev* hdr) {
     __shared__ LocalSmem<T> sm;
-    const int n = hdr->n;
-    char* ws = hdr->ws;
-    int begin, end;
-    batch_share(blockIdx.x, gridDim.x, hdr->total_tiles, begin, end);
-    const auto base = [](const BatchImage& m) { return m.tile_base; };
-    int i = batch_find(imgs, n, begin, base);
-    for (int task = begin; task < end; ++task) {
-        i = batch_advance(imgs, n, i, task, base);
-        const BatchImage& im = imgs[i];
-        const int vec16 = ((uintptr_t)im.edges % 16 == 0) && (im.epitch % 16 == 0);
-        local_tile<T>(batch_args(im, ws), task - im.tile_base, im.tiles_x, vec16, sm);
-        __syncthreads();  // LDS is reused by the next tile
-    }
+    const int task = blockIdx.x;
+    if (task >= hdr->total_tiles) return;
+    const int i = batch_find(imgs, hdr->n, task, [](const BatchImage& m) { return m.tile_base; });
+    const BatchImage& im = imgs[i];
+    const int vec16 = ((uintptr_t)im.edges % 16 == 0) && (im.epitch % 16 == 0);
+    local_tile<T>(batch_args(im, hdr->ws), task - im.tile_base, im.tiles_x, vec16, sm);
 }
 
 template <int T>
@@ -644,9 +635,10 @@ k_hyst_resolve_batch(const BatchImage* imgs, const BatchDev* hdr) {
 }  // namespace
 
 hipError_t launch_hyst_batch(const BatchImage* imgs, const BatchDev* hdr, int total_tiles,
-                             int total_merge, int total_slots, int nwg, hipStream_t s) {
+                             int total_merge, int total_slots, hipStream_t s) {
     constexpr int T = 64;
-    hipLaunchKernelGGL(k_hyst_local_batch<T>, dim3(nwg), dim3(kWGThreads), 0, s, imgs, hdr);
+    hipLaunchKernelGGL(k_hyst_local_batch<T>, dim3(max(total_tiles, 1)), dim3(kWGThreads), 0, s,
+                       imgs, hdr);
     hipLaunchKernelGGL(k_hyst_merge_batch<T>, dim3(ceil_div(max(total_merge, 1), kWGThreads)),
                        dim3(kWGThreads), 0, s, imgs, hdr);
     hipLaunchKernelGGL(k_hyst_flags_batch, dim3(ceil_div(max(total_slots, 1), kWGThreads)),

@@ -160,9 +160,9 @@ struct BatchDev {
     int total_fwd, total_tiles, total_merge, total_slots;
 };
 hipError_t launch_u8_forward_batch(const BatchImage* imgs, const BatchDev* hdr, int rows_per_wave,
-                                   int nwg, hipStream_t s);
+                                   int total_fwd, hipStream_t s);
 hipError_t launch_hyst_batch(const BatchImage* imgs, const BatchDev* hdr, int total_tiles,
-                             int total_merge, int total_slots, int nwg, hipStream_t s);
+                             int total_merge, int total_slots, hipStream_t s);
 
 size_t mag_partials(int N, int H, int W, int radius);
 hipError_t launch_mag_forward(const float* I, const float* sigma, int N, int H, int W, int radius,

@@ -326,28 +326,24 @@ k_u8_forward(U8FwdArgs a, int strips_x, int nwaves, int fast_ok) {
     else walk<R, true>(a, X0, Y0, lane, fast_ok);
 }
 
-// Persistent batch forward: each wave takes a contiguous run of (image,
-// strip, row block) tasks.
+// Batch forward: one wave per (image, strip, row block) task over all
+// images of the batch.
 template <int R>
 __global__ void __launch_bounds__(kWGThreads)
 k_u8_forward_batch(const BatchImage* imgs, const BatchDev* hdr) {
     const int lane = threadIdx.x & (kWave - 1);
     const int n = hdr->n, total = hdr->total_fwd;
     char* ws = hdr->ws;
-    // wave w of nw takes the contiguous task run [begin, end): tasks are
-    // uniform strips, and no shared counter is touched
-    const int nw = gridDim.x * kWavesPerWG;
-    const int w = blockIdx.x * kWavesPerWG + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int begin = (int)((int64_t)total * w / nw);
-    const int end = (int)((int64_t)total * (w + 1) / nw);
-    int lo = 0, hi = n - 1;  // last image whose first task is <= begin
+    // one wave per task (image, strip, row block); the image by binary search
+    const int tk = blockIdx.x * kWavesPerWG + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (tk >= total) return;
+    int lo = 0, hi = n - 1;  // last image whose first task is <= tk
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (imgs[mid].fwd_base <= begin) lo = mid;
+        if (imgs[mid].fwd_base <= tk) lo = mid;
         else hi = mid - 1;
     }
-    for (int tk = begin; tk < end; ++tk) {
-        while (lo + 1 < n && imgs[lo + 1].fwd_base <= tk) ++lo;
+    {
         const BatchImage& im = imgs[lo];
         U8FwdArgs a;
         a.in = im.in;
@@ -372,8 +368,9 @@ k_u8_forward_batch(const BatchImage* imgs, const BatchDev* hdr) {
 
 }  // namespace
 
-hipError_t launch_u8_forward_batch(const BatchImage* imgs, const BatchDev* hdr, int rows, int nwg,
+hipError_t launch_u8_forward_batch(const BatchImage* imgs, const BatchDev* hdr, int rows, int total_fwd,
                                    hipStream_t s) {
+    const int nwg = max(ceil_div(total_fwd, kWavesPerWG), 1);
     switch (rows) {
         case 16: hipLaunchKernelGGL(k_u8_forward_batch<16>, dim3(nwg), dim3(kWGThreads), 0, s, imgs, hdr); break;
         case 48: hipLaunchKernelGGL(k_u8_forward_batch<48>, dim3(nwg), dim3(kWGThreads), 0, s, imgs, hdr); break;
