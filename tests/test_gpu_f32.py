@@ -190,3 +190,19 @@ def test_float_edges_only_path(canny, shape):
     if H * W <= 1 << 20:
         _, _, _, omx = oracle.classify_f32(X, 1.4, 3)
         assert abs(float(mx.cpu()[0]) - omx) <= TOL * omx
+
+
+def test_float_edges_only_absolute_with_max(canny):
+    """Absolute thresholds with the maximum requested also take the signed
+    path; with edges alone the hysteresis pass classifies with the absolute
+    thresholds (and writes the maximum)."""
+    X = workloads.natural_u8(300, 517, seed=91).astype(np.float32)
+    dev = torch.from_numpy(X).cuda()
+    e_fused, mx = canny.canny_f32(dev, 1.4, 3, 20.0, 60.0, False, return_max=True)
+    e_cls, cls = canny.canny_f32(dev, 1.4, 3, 20.0, 60.0, False, return_classes=True)
+    torch.cuda.synchronize()
+    assert torch.equal(e_fused, e_cls)
+    oc, _, amb, omx = oracle.classify_f32(X, 1.4, 3, 20.0, 60.0, False, TOL)
+    c = unpack_classes(cls.cpu().numpy(), *X.shape)
+    assert ((c != oc) & ((amb & 3) == 0)).sum() == 0
+    assert abs(float(mx.cpu()[0]) - omx) <= TOL * omx
