@@ -172,7 +172,8 @@ def test_float_stage_timing(canny):
     assert torch.equal(e, ref_e) and torch.equal(c[:, :nb], ref_c[:, :nb])
 
 
-@pytest.mark.parametrize("shape", [(1, 1), (5, 7), (63, 65), (200, 333), (1001, 2049), (4096, 4096)])
+@pytest.mark.parametrize("shape", [(1, 1), (5, 7), (63, 65), (200, 333), (1001, 2049), (4096, 4096),
+                                   (4320, 7680)])
 def test_float_edges_only_path(canny, shape):
     """Edges alone (no class map or strength requested) take the path where
     the hysteresis pass classifies from the signed strength map; it must give

@@ -1,0 +1,53 @@
+"""CPU checks of the profile summarizer used for profiles/ (no GPU): it reads
+rocprofv3 CSV output, scales counters by the copy kernel's reading, and the
+benchmark's traffic figure is withheld once the walk's sources change."""
+import csv
+import os
+
+import pytest
+
+from paper_1710_07745_amd import profiling
+
+
+def write_counters(d, rows):
+    os.makedirs(d, exist_ok=True)
+    with open(os.path.join(d, "run_counter_collection.csv"), "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(["Kernel_Name", "Counter_Name", "Counter_Value"])
+        for r in rows:
+            w.writerow(r)
+
+
+def test_traffic_scaling(tmp_path, capsys):
+    copy = 256 << 20
+    fd, wd = str(tmp_path / "f"), str(tmp_path / "w")
+    # the copy kernel reads half its bytes on FETCH_SIZE (KiB) and all on WRITE_SIZE
+    write_counters(fd, [["__amd_rocclr_copyBuffer", "FETCH_SIZE", copy / 2048],
+                        ["k_walk<3>(args)", "FETCH_SIZE", 100.0],
+                        ["k_walk<3>(args)", "FETCH_SIZE", 300.0],
+                        ["k_walk<3>(args)", "FETCH_SIZE", 200.0]])
+    write_counters(wd, [["__amd_rocclr_copyBuffer", "WRITE_SIZE", copy / 1024],
+                        ["k_walk<3>(args)", "WRITE_SIZE", 50.0]])
+    profiling.main(["traffic", fd, wd, "--kernel", "k_walk<3>", "--copy-bytes", str(copy),
+                    "--alg-bytes", "1024"])
+    out = dict(ln.split(":", 1) for ln in capsys.readouterr().out.splitlines() if not ln.startswith("#"))
+    assert float(out["fetch_scale"]) == pytest.approx(2.0)
+    assert float(out["write_scale"]) == pytest.approx(1.0)
+    # medians 200 and 50 KiB -> 2 * 200 KiB + 50 KiB
+    assert float(out["traffic_bytes_per_launch"]) == pytest.approx((2 * 200 + 50) * 1024)
+    assert out["source_sha256"].strip() == profiling.walk_source_hash()
+
+
+def test_read_traffic_needs_matching_sources(tmp_path):
+    p = tmp_path / "t.txt"
+    p.write_text(f"source_sha256: {profiling.walk_source_hash()}\ntraffic_bytes_per_launch: 1234\n")
+    assert profiling.read_traffic(str(p)) == 1234.0
+    p.write_text("source_sha256: deadbeef\ntraffic_bytes_per_launch: 1234\n")
+    assert profiling.read_traffic(str(p)) is None
+    assert profiling.read_traffic(str(tmp_path / "missing.txt")) is None
+
+
+def test_committed_traffic_summary_parses():
+    path = os.path.join(profiling.ROOT, "profiles", "f32_walk_4096_traffic.txt")
+    kv = dict(ln.split(":", 1) for ln in open(path) if ":" in ln and not ln.startswith("#"))
+    assert float(kv["traffic_bytes_per_launch"]) > float(kv["algorithmic_bytes_per_launch"]) > 0
