@@ -53,6 +53,7 @@ struct canny_batch_plan {
     BatchDev hdr{};
     BatchImage* d_imgs = nullptr;
     BatchDev* d_hdr = nullptr;
+    int32_t* d_tile_img = nullptr;  // per tile: index of its image (fixed by the sizes)
     BatchImage* h_stage = nullptr;  // pinned staging of the descriptor table
     BatchDev* h_stage_hdr = nullptr;
     hipEvent_t uploaded = nullptr;
@@ -268,6 +269,7 @@ void release(canny_batch_plan* p) {
     if (p->uploaded) (void)hipEventDestroy(p->uploaded);
     if (p->d_imgs) (void)hipFree(p->d_imgs);
     if (p->d_hdr) (void)hipFree(p->d_hdr);
+    if (p->d_tile_img) (void)hipFree(p->d_tile_img);
     if (p->h_stage) (void)hipHostFree(p->h_stage);
     if (p->h_stage_hdr) (void)hipHostFree(p->h_stage_hdr);
     delete p;
@@ -309,6 +311,17 @@ int canny_batch_plan_create(int n, const int32_t* H, const int32_t* W, int32_t l
     set_fwd_rows(*p, 32);
     e = hipMalloc(&p->d_imgs, sizeof(BatchImage) * n);
     if (e == hipSuccess) e = hipMalloc(&p->d_hdr, sizeof(BatchDev));
+    if (e == hipSuccess && p->hdr.total_tiles > 0) {  // tile -> image: one load, no search
+        std::vector<int32_t> ti((size_t)p->hdr.total_tiles);
+        for (int i = 0; i < n; ++i) {
+            const BatchImage& m = p->imgs[i];
+            for (int k = 0; k < m.tiles_x * m.tiles_y; ++k) ti[(size_t)m.tile_base + k] = i;
+        }
+        e = hipMalloc(&p->d_tile_img, sizeof(int32_t) * ti.size());
+        if (e == hipSuccess)
+            e = hipMemcpy(p->d_tile_img, ti.data(), sizeof(int32_t) * ti.size(), hipMemcpyHostToDevice);
+        p->hdr.tile_img = p->d_tile_img;
+    }
     if (e == hipSuccess) e = hipHostMalloc(&p->h_stage, sizeof(BatchImage) * n, hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc(&p->h_stage_hdr, sizeof(BatchDev), hipHostMallocDefault);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&p->uploaded, hipEventDisableTiming);

@@ -549,51 +549,16 @@ __device__ __forceinline__ HystArgs batch_args(const BatchImage& im, char* ws) {
     return a;
 }
 
-// last image whose running count (selected by Get) is <= v
-template <typename Get>
-__device__ __forceinline__ int batch_find(const BatchImage* imgs, int n, int v, Get get) {
-    int lo = 0, hi = n - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (get(imgs[mid]) <= v) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
-
-// image of item v for a run of increasing items: start from the image of the
-// previous item (i) and step forward (at most n - 1 steps in total)
-template <typename Get>
-__device__ __forceinline__ int batch_advance(const BatchImage* imgs, int n, int i, int v, Get get) {
-    while (i + 1 < n && get(imgs[i + 1]) <= v) ++i;
-    return i;
-}
-
-// image of a flat-grid item: one search per wave (uniform), then each lane
-// steps forward past the image boundaries inside the wave's 64 items
-template <typename Get>
-__device__ __forceinline__ int batch_find_wave(const BatchImage* imgs, int n, int v, Get get) {
-    const int v0 = __builtin_amdgcn_readfirstlane(v);
-    const int i0 = batch_find(imgs, n, v0, get);
-    return batch_advance(imgs, n, i0, v, get);
-}
-
-// contiguous share [begin, end) of `total` items for worker w of nw
-__device__ __forceinline__ void batch_share(int w, int nw, int total, int& begin, int& end) {
-    begin = (int)((int64_t)total * w / nw);
-    end = (int)((int64_t)total * (w + 1) / nw);
-}
-
-// Local pass over the batch: one workgroup per tile, the image found by a
-// binary search over the tile bases.
+// Batch passes: flat grids over all images; a tile's image comes from the
+// plan's tile -> image table (merge items and border slots are 128 and 256
+// per tile, in tile order, so they index the same table).
 template <int T>
 __global__ void __launch_bounds__(kWGThreads)
 k_hyst_local_batch(const BatchImage* imgs, const BatchDev* hdr) {
     __shared__ LocalSmem<T> sm;
     const int task = blockIdx.x;
     if (task >= hdr->total_tiles) return;
-    const int i = batch_find(imgs, hdr->n, task, [](const BatchImage& m) { return m.tile_base; });
-    const BatchImage& im = imgs[i];
+    const BatchImage& im = imgs[hdr->tile_img[task]];
     const int vec16 = ((uintptr_t)im.edges % 16 == 0) && (im.epitch % 16 == 0);
     local_tile<T>(batch_args(im, hdr->ws), task - im.tile_base, im.tiles_x, vec16, sm);
 }
@@ -601,10 +566,8 @@ k_hyst_local_batch(const BatchImage* imgs, const BatchDev* hdr) {
 template <int T>
 __global__ void __launch_bounds__(kWGThreads) k_hyst_merge_batch(const BatchImage* imgs, const BatchDev* hdr) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    const int i = batch_find_wave(imgs, hdr->n, min(g, hdr->total_merge - 1),
-                                  [](const BatchImage& m) { return m.merge_base; });
     if (g >= hdr->total_merge) return;
-    const BatchImage& im = imgs[i];
+    const BatchImage& im = imgs[hdr->tile_img[g / (T + kHystCols)]];
     const int local = g - im.merge_base;
     const int tile = local / (T + kHystCols);
     merge_one<T>(batch_args(im, hdr->ws), tile, local - tile * (T + kHystCols), im.tiles_x, im.tiles_y);
@@ -612,10 +575,9 @@ __global__ void __launch_bounds__(kWGThreads) k_hyst_merge_batch(const BatchImag
 
 __global__ void __launch_bounds__(kWGThreads) k_hyst_flags_batch(const BatchImage* imgs, const BatchDev* hdr) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    const int i = batch_find_wave(imgs, hdr->n, min(g, hdr->total_slots - 1),
-                                  [](const BatchImage& m) { return m.slot_base; });
     if (g >= hdr->total_slots) return;
-    flags_one(batch_args(imgs[i], hdr->ws), g - imgs[i].slot_base);
+    const BatchImage& im = imgs[hdr->tile_img[g / Tile<64>::kPerim]];
+    flags_one(batch_args(im, hdr->ws), g - im.slot_base);
 }
 
 template <int T>
@@ -626,8 +588,7 @@ k_hyst_resolve_batch(const BatchImage* imgs, const BatchDev* hdr) {
     __shared__ uint8_t res[kWGThreads];
     const int task = blockIdx.x;
     if (task >= hdr->total_tiles) return;
-    const int i = batch_find(imgs, hdr->n, task, [](const BatchImage& m) { return m.tile_base; });
-    const BatchImage& im = imgs[i];
+    const BatchImage& im = imgs[hdr->tile_img[task]];
     const int vec16 = ((uintptr_t)im.edges % 16 == 0) && (im.epitch % 16 == 0);
     resolve_tile<T>(batch_args(im, hdr->ws), task - im.tile_base, im.tiles_x, vec16, res);
 }

@@ -155,6 +155,7 @@ struct BatchImage {
 };
 struct BatchDev {
     char* ws;
+    const int32_t* tile_img;  // image index of every tile of the batch (tile_base order)
     int n;
     int low, high;
     int total_fwd, total_tiles, total_merge, total_slots;
