@@ -142,9 +142,8 @@ int canny_f32(const float* in, int64_t in_pitch, int H, int W, float sigma, int 
  * plan fixes the image sizes and thresholds, picks tile shapes (from an
  * on-disk autotune cache, by timing candidates when autotune != 0, else a
  * default), and records one HIP graph whose kernels each cover every tile
- * of every image in a single launch (the forward and the local labelling
- * are persistent: each wave or workgroup takes a contiguous share of the
- * batch's strips or tiles).
+ * of every image in a single flat launch (one wave per forward task, one
+ * workgroup per hysteresis tile, one thread per border pixel or slot).
  * canny_batch writes the per-image pointer table to the device and replays
  * the graph on `stream`.
  *

@@ -136,8 +136,8 @@ def canny_f32(img: torch.Tensor, sigma: float = 1.4, radius: int = 3, low: float
 
 
 class BatchPlan:
-    """Batched integer Canny over images of uneven sizes: one persistent launch
-    per phase, replayed from a recorded HIP graph.  See canny_batch_plan_create."""
+    """Batched integer Canny over images of uneven sizes: one flat launch per
+    phase, replayed from a recorded HIP graph.  See canny_batch_plan_create."""
 
     def __init__(self, shapes: Sequence[Sequence[int]], low: int = 40, high: int = 100,
                  autotune: bool = False, device=None):

@@ -3,13 +3,12 @@
 //
 // A plan fixes the sizes and thresholds and lays out one workspace region per
 // image (class map + hysteresis state).  Every phase of the detector runs as
-// ONE launch over all images: the forward and the local hysteresis pass are
-// persistent kernels: each wave (forward) or workgroup (tiles) takes a
-// contiguous share of the batch's work items, which are uniform strips /
-// tiles, so large and small images interleave freely and no shared counter
-// is touched; the two per-border-pixel passes and the resolve pass (one
-// workgroup per tile, most of which exit at once) are flat grids over all
-// images.  The launches are recorded once into a HIP graph
+// ONE flat launch over all images: one wave per forward task (a strip and row
+// block of one image), one workgroup per hysteresis tile for the local and
+// resolve passes, one thread per border pixel or slot for merge and flags.
+// Work items are uniform, so large and small images interleave freely and no
+// shared counter is touched; a tile's image comes from a per-plan
+// tile -> image table.  The launches are recorded once into a HIP graph
 //     forward -> local -> merge -> flags -> resolve
 // whose kernels read a device descriptor table; a call uploads the table
 // (the caller's image pointers and workspace) and replays the graph, so new
