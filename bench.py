@@ -85,7 +85,7 @@ def roofline_headline(canny, torch, bufs, H, W, steps):
     same rotating buffers, after the timed one).  The dominant kernel is the
     float walk (Gaussian, Sobel, strength, suppression); its algorithmic bytes
     are the float forward's 4 B/px in + 0.25 B/px of class map out."""
-    from paper_1710_07745_amd.profiling import read_traffic
+    from paper_1710_07745_amd.profiling import WALK_KERNEL, read_traffic
     xs, es, ws = bufs
     k = len(xs)
     with canny.StageTiming(steps) as t:
@@ -102,7 +102,7 @@ def roofline_headline(canny, torch, bufs, H, W, steps):
     fwd_s = (us["f32_minmax"] + us["f32_walk"] + us["f32_classify"]) * 1e-6
     return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": read_traffic(TRAFFIC_FILE),
-            "kernel": "k_f32_forward<3, 36, true> (float walk: blur, Sobel, strength, "
+            "kernel": WALK_KERNEL + " (float walk: blur, Sobel, strength, "
                       "suppression; 4096x4096)",
             "bytes_per_launch": alg, "avg_launch_us": us["f32_walk"],
             "stage_avg_us": us,

@@ -83,6 +83,24 @@ struct WalkShape {
 // true handles strips and rows that touch the image border: clamped loads,
 // edge columns copied outward, and the rows above row 0 / below row H-1
 // replaced by the edge row where a stage reads them.
+typedef float f32x4v __attribute__((ext_vector_type(4)));
+typedef unsigned u32x4v __attribute__((ext_vector_type(4)));
+
+// Work split of a balanced walk launch (large images).  Strips that touch the
+// left or right border (or every strip when rows are not 16-byte aligned),
+// and the top and bottom row blocks of the others, take the border variant,
+// which costs about 1.5x the interior one per row; so border blocks are RRE
+// rows tall and interior blocks RRI > RRE rows, which evens out the waves'
+// durations (with one block height the border waves set the kernel's end).
+//   waves [0, edge_waves): border strips {0} and [sr, strips_x), block-major;
+//   the rest: interior strips [1, sr), block-major, per strip one top border
+//   block [0, RRE), k interior blocks from row RRE, then nb border blocks.
+struct WalkPlan {
+    int nwaves, edge_waves;
+    int n_es, sr, n_is;  // border strips, first right border strip, interior strips
+    int k, nb;           // interior / bottom border blocks per interior strip
+};
+
 template <int R, int RR, bool SIGNED, bool EDGE>
 __device__ __forceinline__ void f32_walk(const F32FwdArgs& a, int X0, int Y0, int lane, int fast_ok) {
     constexpr int HL = WalkShape<R>::HL;
@@ -112,6 +130,7 @@ __device__ __forceinline__ void f32_walk(const F32FwdArgs& a, int X0, int Y0, in
         bd.outR[k] = c0 + k >= W;
     }
     const bool out_lane = lane >= HL && lane < kWave - HL;
+    const uint32_t soff = out_lane ? (uint32_t)c0 * 4u : 0x80000000u;
 
     float g[R + 1];
 #pragma unroll
@@ -145,12 +164,11 @@ __device__ __forceinline__ void f32_walk(const F32FwdArgs& a, int X0, int Y0, in
         float lo = 3.402823466e38f, hi = -3.402823466e38f;
 #pragma unroll
         for (int u = 0; u < kF32RangeParts / kWave; ++u) {  // all loads in flight at once
-            const int j = lane + u * kWave;
-            if (j < a.nrange) {
-                const float2 p = a.range[j];
-                lo = fminf(lo, p.x);
-                hi = fmaxf(hi, p.y);
-            }
+            // clamped, not guarded: a repeated partial leaves min and max unchanged
+            // and every load is unconditional, so all are in flight together
+            const float2 p = a.range[min(lane + u * kWave, a.nrange - 1)];
+            lo = fminf(lo, p.x);
+            hi = fmaxf(hi, p.y);
         }
         off = 0.5f * wave_min(lo) + 0.5f * wave_max(hi);
     } else {
@@ -224,7 +242,15 @@ __device__ __forceinline__ void f32_walk(const F32FwdArgs& a, int X0, int Y0, in
                     mmax = fmaxf(mmax, rmax);
                     __asm__ volatile("" : "+v"(mmax));
                 }
-                if (out_lane && (!EDGE || c0 < W)) {
+                if (SIGNED && !EDGE) {
+                    // unconditional buffer store: halo lanes carry an offset past the
+                    // descriptor's range, so the hardware drops their writes; no branch
+                    // around the store keeps the load-wait counts exact
+                    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                        a.smag + (int64_t)n * a.spitch, (short)0, 0x7fffffff, 0x00020000);
+                    f32x4v q = {sv.v[0], sv.v[1], sv.v[2], sv.v[3]};
+                    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4v, q), rs, (int)soff, 0, 0);
+                } else if (out_lane && (!EDGE || c0 < W)) {
                     if (SIGNED) {
                         // row pitch is W rounded up to 4, so the quad store stays inside the row
                         *reinterpret_cast<float4*>(a.smag + (int64_t)n * a.spitch + c0) =
@@ -338,6 +364,50 @@ k_f32_forward(F32FwdArgs a, int strips_x, int nwaves, int fast_ok) {
         f32_walk<R, RR, SIGNED, false>(a, X0, Y0, lane, fast_ok);
     else
         f32_walk<R, RR, SIGNED, true>(a, X0, Y0, lane, fast_ok);
+}
+
+// Balanced launch: interior blocks of RRI rows, border blocks of RRE rows
+// (see WalkPlan).  The task decides the variant; the interior conditions hold
+// by construction and are checked again before the unclamped walk.
+template <int R, int RRI, int RRE, bool SIGNED>
+__global__ void __launch_bounds__(kWGThreads) __attribute__((amdgpu_waves_per_eu(R >= 6 ? 2 : 3)))
+k_f32_forward_bal(F32FwdArgs a, WalkPlan p, int fast_ok) {
+    constexpr int HL = WalkShape<R>::HL;
+    constexpr int SC = WalkShape<R>::SC;
+    constexpr int HR = WalkShape<R>::HR;
+    static_assert(RRE >= HR, "the top border block must cover the interior blocks' upper halo");
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave_in_wg = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wg = xcd_remap(blockIdx.x, gridDim.x);
+    const int wave = wg * kWavesPerWG + wave_in_wg;
+    if (wave >= p.nwaves) return;
+    int X0, Y0;
+    bool interior = false;
+    if (wave < p.edge_waves) {
+        const int es = wave % p.n_es;
+        X0 = (es == 0 ? 0 : p.sr + es - 1) * SC;
+        Y0 = (wave / p.n_es) * RRE;
+    } else {
+        const int w = wave - p.edge_waves;
+        const int blk = w / p.n_is;
+        X0 = (1 + w % p.n_is) * SC;
+        if (blk == 0) {
+            Y0 = 0;
+        } else if (blk <= p.k) {
+            Y0 = RRE + (blk - 1) * RRI;
+            interior = true;
+        } else {
+            Y0 = RRE + p.k * RRI + (blk - 1 - p.k) * RRE;
+        }
+    }
+    if (interior) {
+        if (!(fast_ok && X0 - 4 * HL >= 0 && X0 + SC + 4 * HL <= a.W && Y0 - HR >= 0 &&
+              Y0 + RRI + HR <= a.H))
+            return;  // unreachable for a plan from make_walk_plan
+        f32_walk<R, RRI, SIGNED, false>(a, X0, Y0, lane, fast_ok);
+    } else {
+        f32_walk<R, RRE, SIGNED, true>(a, X0, Y0, lane, fast_ok);
+    }
 }
 
 constexpr int kRowThreads = 256;  // one workgroup walks whole rows
@@ -479,16 +549,47 @@ void launch_walk(const F32FwdArgs& a, int fast_ok, hipStream_t s) {
                        strips_x, nwaves, fast_ok);
 }
 
+constexpr int kRRI = 40, kRRE = 23;  // balanced block heights (interior, border)
+
+template <int R>
+WalkPlan make_walk_plan(int H, int W, int fast_ok) {
+    constexpr int SC = WalkShape<R>::SC, HL = WalkShape<R>::HL;
+    WalkPlan p{};
+    const int strips_x = ceil_div(W, SC);
+    int sr = strips_x;  // first strip whose right halo leaves the image
+    if (!fast_ok) {
+        sr = 1;
+    } else {
+        for (int s = 1; s < strips_x; ++s)
+            if ((int64_t)(s + 1) * SC + 4 * HL > W) {
+                sr = s;
+                break;
+            }
+    }
+    if (strips_x == 1) sr = 1;
+    p.sr = sr;
+    p.n_es = 1 + (strips_x - sr);
+    p.n_is = sr - 1;
+    p.k = H >= 2 * kRRE ? (H - 2 * kRRE) / kRRI : 0;
+    p.nb = ceil_div(max(0, H - kRRE - p.k * kRRI), kRRE);
+    p.edge_waves = p.n_es * ceil_div(H, kRRE);
+    p.nwaves = p.edge_waves + p.n_is * (1 + p.k + p.nb);
+    return p;
+}
+
 // Rows per wave: a wave walks its strip serially, so long strips suit large
 // images (halo rows amortised) and short ones small images (more waves in
-// flight).  36 unless that leaves fewer than 1024 waves (one per SIMD).
+// flight).  The balanced split unless that leaves fewer than 1024 waves (one
+// per SIMD); then 8 rows per wave.
 template <int R, bool SIGNED>
 void launch_walk_sized(const F32FwdArgs& a, int fast_ok, hipStream_t s) {
-    const int strips_x = ceil_div(a.W, WalkShape<R>::SC);
-    if ((int64_t)strips_x * ceil_div(a.H, 36) >= 1024)
-        launch_walk<R, 36, SIGNED>(a, fast_ok, s);
-    else
+    const WalkPlan p = make_walk_plan<R>(a.H, a.W, fast_ok);
+    if (p.nwaves >= 1024) {
+        hipLaunchKernelGGL((k_f32_forward_bal<R, kRRI, kRRE, SIGNED>), dim3(ceil_div(p.nwaves, kWavesPerWG)),
+                           dim3(kWGThreads), 0, s, a, p, fast_ok);
+    } else {
         launch_walk<R, 8, SIGNED>(a, fast_ok, s);
+    }
 }
 
 template <int R>

@@ -154,6 +154,38 @@ def test_float_7680x4320(canny):
     check_float(canny, X)
 
 
+# Shapes for the balanced walk launch (interior blocks of 40 rows, border
+# blocks of 23): images under 23 rows (one border block per strip), exactly
+# 46 rows (no interior block), 60 rows (no interior block, two bottom border
+# blocks), three border strips (right halo of the second-to-last strip leaves
+# the image), and every strip bordered (rows not 16-byte aligned).
+@pytest.mark.parametrize("shape", [(22, 245760), (46, 123000), (60, 82000), (3000, 4084)])
+@pytest.mark.parametrize("relative", [True, False])
+def test_float_balanced_split(canny, shape, relative):
+    X = workloads.natural_u8(*shape, seed=shape[0] + shape[1]).astype(np.float32)
+    if relative:
+        check_float(canny, X)
+    else:
+        lo, hi = absolute_like_relative(X)
+        check_float(canny, X, low=lo, high=hi, relative=False, with_max=False)
+
+
+def test_float_balanced_split_unaligned(canny):
+    X = workloads.natural_u8(2048, 4096, seed=41).astype(np.float32)
+    H, W = X.shape
+    big = torch.zeros((H, W + 3), dtype=torch.float32, device="cuda")
+    big[:, 1:W + 1] = torch.from_numpy(X).cuda()
+    e, cls, mag = canny.canny_f32(big[:, 1:W + 1], 1.4, 3, 0.05, 0.15, True, return_classes=True,
+                                  return_magnitude=True)
+    c = unpack_classes(cls.cpu().numpy(), H, W)
+    oc, oM, amb, omx = oracle.classify_f32(X, 1.4, 3, 0.05, 0.15, True, TOL)
+    err = np.abs(mag.cpu().numpy() - oM) / np.maximum(oM, 0.05 * omx)
+    assert err.max() <= TOL
+    assert ((c != oc) & ((amb & 3) == 0)).sum() == 0
+    be, _ = oracle.hysteresis(c)
+    assert np.array_equal(e.cpu().numpy(), be)
+
+
 def test_float_stage_timing(canny):
     """Stage timing records one event pair per stage and call and leaves the
     results unchanged."""
