@@ -93,13 +93,13 @@ def roofline_headline(canny, torch, bufs, H, W, steps):
             canny.canny_f32(xs[i % k], 1.4, 3, 0.05, 0.15, True, edges=es[i % k], workspace=ws)
         torch.cuda.synchronize()
         us = {}
-        for name in ("f32_minmax", "f32_walk", "f32_classify", "hysteresis"):
+        for name in ("f32_clear", "f32_walk", "f32_classify", "hysteresis"):
             ms, n = t.read(name)
             us[name] = round(ms * 1e3 / max(n, 1), 2)
     alg = H * W * (4 + 0.25)
     walk_s = us["f32_walk"] * 1e-6
     gbs = alg / walk_s / 1e9
-    fwd_s = (us["f32_minmax"] + us["f32_walk"] + us["f32_classify"]) * 1e-6
+    fwd_s = (us["f32_clear"] + us["f32_walk"] + us["f32_classify"]) * 1e-6
     return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": read_traffic(TRAFFIC_FILE),
             "kernel": WALK_KERNEL + " (float walk: blur, Sobel, strength, "

@@ -52,7 +52,7 @@ enum {
 /* Human-readable name of a status code (static string, never NULL). */
 const char* canny_status_string(int status);
 
-/* Library ABI version (incremented on any signature change). */
+/* Library ABI version (incremented on any signature or enum change). */
 int canny_abi_version(void);
 
 /* Row pitch in bytes of the 2-bit class map for width W:
@@ -208,7 +208,8 @@ int canny_mag_backward(const float* I, const float* sigma, const float* dM, int 
  *   number of recorded launches.
  * canny_timing_end(): stops recording and destroys the events.
  * Stages: CANNY_STAGE_U8_FORWARD (canny_u8 Steps 1-3 + thresholds),
- *   CANNY_STAGE_F32_MINMAX (input range pass of canny_f32),
+ *   CANNY_STAGE_F32_CLEAR (canny_f32: the one-thread launch that clears the
+ *   largest-strength word before the walk),
  *   CANNY_STAGE_F32_WALK (canny_f32 Steps 1-3: the blur/Sobel/suppression
  *   kernel), CANNY_STAGE_F32_CLASSIFY (canny_f32 thresholds pass),
  *   CANNY_STAGE_HYSTERESIS (all hysteresis kernels of canny_u8, canny_f32,
@@ -219,7 +220,7 @@ int canny_mag_backward(const float* I, const float* sigma, const float* dM, int 
  */
 enum {
     CANNY_STAGE_U8_FORWARD = 0,
-    CANNY_STAGE_F32_MINMAX = 1,
+    CANNY_STAGE_F32_CLEAR = 1,
     CANNY_STAGE_F32_WALK = 2,
     CANNY_STAGE_F32_CLASSIFY = 3,
     CANNY_STAGE_HYSTERESIS = 4,

@@ -50,7 +50,7 @@ SIGNATURES = {
 }
 
 # stage ids of canny_timing_read (include/canny.h)
-STAGES = {"u8_forward": 0, "f32_minmax": 1, "f32_walk": 2, "f32_classify": 3, "hysteresis": 4,
+STAGES = {"u8_forward": 0, "f32_clear": 1, "f32_walk": 2, "f32_classify": 3, "hysteresis": 4,
           "mag_forward": 5, "mag_backward": 6}
 
 

@@ -74,7 +74,7 @@ const char* canny_status_string(int status) {
     }
 }
 
-int canny_abi_version(void) { return 2; }
+int canny_abi_version(void) { return 3; }
 
 int64_t canny_class_pitch(int W) { return class_pitch(W); }
 
@@ -153,7 +153,7 @@ int canny_hysteresis(const uint8_t* class2, int H, int W, uint8_t* edges, int64_
 
 static int64_t smag_pitch(int W) { return ((int64_t)W + 3) & ~(int64_t)3; }
 // float workspace: largest-strength word, then the min/max partials
-static constexpr size_t kF32Header = 256 + align256(kF32RangeParts * sizeof(float2));
+static constexpr size_t kF32Header = 256;  // the largest-strength word
 
 size_t canny_f32_workspace_bytes(int H, int W) {
     if (!size_ok(H, W)) return 0;
@@ -198,7 +198,6 @@ int canny_f32(const float* in, int64_t in_pitch, int H, int W, float sigma, int 
     f.high = high;
     f.relative = relative ? 1 : 0;
     f.maxbits = reinterpret_cast<uint32_t*>(w);
-    f.range = reinterpret_cast<float2*>(w + 256);
     const size_t hyst_off = kF32Header + class_bytes(H, W);
     if (relative || max_out) {  // the walk stores signed strengths, a second pass classifies
         f.smag = reinterpret_cast<float*>(w + hyst_off +

@@ -15,8 +15,8 @@
 // Relative thresholds need the image's largest strength before any pixel
 // can be classified.  With absolute thresholds one launch classifies
 // directly.  With relative thresholds (or when the largest strength is
-// requested) the path is: a memory-bound min/max pass over the input, the
-// walk with a threshold-free epilogue that stores the strength with its sign
+// requested) the path is: a one-thread launch that clears the largest-strength
+// word, the walk with a threshold-free epilogue that stores the strength with its sign
 // carrying the suppression decision (+M kept, -M suppressed) and reduces the
 // largest M into one word (atomicMax on the float bits, order-independent
 // because the value is non-negative), then an elementwise pass that derives
@@ -25,9 +25,9 @@
 //
 // Accuracy: every stage before the strength is linear, and Sobel ignores a
 // constant offset, so the walk filters X - c instead of X, with c the
-// midpoint of the image's value range (from the min/max pass; without it,
-// the midpoint of the wave's first input row).  That halves the magnitude
-// the fp32 accumulations round at, and a constant image gives exactly zero.
+// midpoint of the value range of the wave's first input row.  On images whose
+// rows span the value range that halves the magnitude the fp32 accumulations
+// round at (never more than |X| itself), and a constant image gives exactly zero.
 //
 // Suppression interpolates along the continuous gradient direction: with
 // t = min(|Gx|,|Gy|) / max(|Gx|,|Gy|) and same = (Gx*Gy > 0),
@@ -160,18 +160,7 @@ __device__ __forceinline__ void f32_walk(const F32FwdArgs& a, int X0, int Y0, in
 
     // offset c subtracted from every input value (see the file comment)
     float off;
-    if (SIGNED) {  // image range from the min/max pass's per-workgroup partials
-        float lo = 3.402823466e38f, hi = -3.402823466e38f;
-#pragma unroll
-        for (int u = 0; u < kF32RangeParts / kWave; ++u) {  // all loads in flight at once
-            // clamped, not guarded: a repeated partial leaves min and max unchanged
-            // and every load is unconditional, so all are in flight together
-            const float2 p = a.range[min(lane + u * kWave, a.nrange - 1)];
-            lo = fminf(lo, p.x);
-            hi = fmaxf(hi, p.y);
-        }
-        off = 0.5f * wave_min(lo) + 0.5f * wave_max(hi);
-    } else {
+    {
         const F4& r0 = in[0];
         const float lo = wave_min(fminf(fminf(r0.v[0], r0.v[1]), fminf(r0.v[2], r0.v[3])));
         const float hi = wave_max(fmaxf(fmaxf(r0.v[0], r0.v[1]), fmaxf(r0.v[2], r0.v[3])));
@@ -229,7 +218,12 @@ __device__ __forceinline__ void f32_walk(const F32FwdArgs& a, int X0, int Y0, in
                     const float ms = mc * mxv;
                     const bool keep = mc > 0.0f && ms > behind && ms >= ahead;
                     if (SIGNED) {
-                        sv.v[k] = keep ? mc : -mc;
+                        // two selects on compare results instead of one on their
+                        // conjunction (no scalar mask arithmetic between vector ops);
+                        // M = 0 gives +-0, which reads as not kept (only > 0 is)
+                        float t = ms >= ahead ? mc : -mc;
+                        __asm__("" : "+v"(t));
+                        sv.v[k] = ms > behind ? t : -mc;
                         if (!EDGE || !bd.outR[k]) rmax = fmaxf(rmax, mc);
                     } else {
                         const uint32_t code = (keep && mc > a.high) ? 2u : ((keep && mc >= a.low) ? 1u : 0u);
@@ -413,73 +407,14 @@ k_f32_forward_bal(F32FwdArgs a, WalkPlan p, int fast_ok) {
 constexpr int kRowThreads = 256;  // one workgroup walks whole rows
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ float min4(f32x4 v) { return fminf(fminf(v.x, v.y), fminf(v.z, v.w)); }
-__device__ __forceinline__ float max4(f32x4 v) { return fmaxf(fmaxf(v.x, v.y), fmaxf(v.z, v.w)); }
 
 constexpr int kRowBatch = 8;  // rows a thread reads per batch (loads in flight)
 
-// Input min and max, one (min, max) pair per workgroup written to
-// a.range[blockIdx.x] (no atomics: the walk reduces the pairs itself).
-// Workgroup b owns a contiguous run of ceil(H / gridDim.x) rows; a thread
-// takes quad columns q = threadIdx.x + 256 j of those rows, kRowBatch rows
-// per batch so that that many loads are in flight.  Also clears the largest-strength word the
-// walk reduces into, which is safe because the walk is launched after this
-// kernel.
-__global__ void __launch_bounds__(kRowThreads)
-k_f32_minmax(F32FwdArgs a, int quads_ok) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) *a.maxbits = 0u;
-    float lo = 3.402823466e38f, hi = -3.402823466e38f;
-    const int W = a.W;
-    const int chunk = (a.H + (int)gridDim.x - 1) / (int)gridDim.x;
-    const int y0 = (int)blockIdx.x * chunk;
-    const int nrows = max(0, min(chunk, a.H - y0));
-    const int64_t rstride = a.pitch;
-    const float* base = a.in + (int64_t)y0 * a.pitch;
-    if (quads_ok) {
-        const int nq = W >> 2;
-        for (int q = threadIdx.x; q < nq; q += kRowThreads) {
-            for (int k0 = 0; k0 < nrows; k0 += kRowBatch) {
-                f32x4 v[kRowBatch];
-#pragma unroll
-                for (int u = 0; u < kRowBatch; ++u)
-                    if (k0 + u < nrows) v[u] = reinterpret_cast<const f32x4*>(base + (k0 + u) * rstride)[q];
-#pragma unroll
-                for (int u = 0; u < kRowBatch; ++u) {
-                    if (k0 + u < nrows) {
-                        lo = fminf(lo, min4(v[u]));
-                        hi = fmaxf(hi, max4(v[u]));
-                    }
-                }
-            }
-        }
-        for (int x = 4 * nq + threadIdx.x; x < W; x += kRowThreads) {  // ragged tail columns
-            for (int k = 0; k < nrows; ++k) {
-                lo = fminf(lo, base[k * rstride + x]);
-                hi = fmaxf(hi, base[k * rstride + x]);
-            }
-        }
-    } else {
-        for (int x = threadIdx.x; x < W; x += kRowThreads) {
-            for (int k = 0; k < nrows; ++k) {
-                lo = fminf(lo, base[k * rstride + x]);
-                hi = fmaxf(hi, base[k * rstride + x]);
-            }
-        }
-    }
-    __shared__ float2 part[kRowThreads / kWave];
-    lo = wave_min(lo);
-    hi = wave_max(hi);
-    const int wv = threadIdx.x / kWave;
-    if ((threadIdx.x & (kWave - 1)) == 0) part[wv] = make_float2(lo, hi);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        float2 r = part[0];
-        for (int k = 1; k < kRowThreads / kWave; ++k) {
-            r.x = fminf(r.x, part[k].x);
-            r.y = fmaxf(r.y, part[k].y);
-        }
-        a.range[blockIdx.x] = r;
-    }
+// Clears the largest-strength word the walk reduces into (atomicMax of
+// non-negative float bits); a kernel rather than a memset, so the sequence
+// can be recorded into a graph and replayed.
+__global__ void __launch_bounds__(kWave) k_f32_clear_max(uint32_t* maxbits) {
+    if (threadIdx.x == 0) *maxbits = 0u;
 }
 
 // Thresholds and classes from the signed strength map: a pixel is kept iff
@@ -600,19 +535,17 @@ hipError_t launch_radius(const F32FwdArgs& a, hipStream_t s) {
         launch_walk_sized<R, false>(a, fast_ok, s);
         return hipGetLastError();
     }
-    F32FwdArgs b = a;
-    b.nrange = min(a.H, kF32RangeParts);
     {
-        StageTimer t(CANNY_STAGE_F32_MINMAX, s);
-        hipLaunchKernelGGL(k_f32_minmax, dim3(b.nrange), dim3(kRowThreads), 0, s, b, fast_ok);
+        StageTimer t(CANNY_STAGE_F32_CLEAR, s);
+        hipLaunchKernelGGL(k_f32_clear_max, dim3(1), dim3(kWave), 0, s, a.maxbits);
     }
     {
         StageTimer t(CANNY_STAGE_F32_WALK, s);
-        launch_walk_sized<R, true>(b, fast_ok, s);
+        launch_walk_sized<R, true>(a, fast_ok, s);
     }
     if (!a.skip_classify) {
         StageTimer t(CANNY_STAGE_F32_CLASSIFY, s);
-        hipLaunchKernelGGL(k_f32_classify, dim3(rows_grid(a.H)), dim3(kRowThreads), 0, s, b);
+        hipLaunchKernelGGL(k_f32_classify, dim3(rows_grid(a.H)), dim3(kRowThreads), 0, s, a);
     }
     return hipGetLastError();
 }

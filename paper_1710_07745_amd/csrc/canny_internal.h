@@ -112,8 +112,6 @@ struct F32FwdArgs {
     float low, high;
     int relative;
     uint32_t* maxbits;  // device word: float bits of the largest M (>= 0)
-    float2* range;      // per-workgroup (min, max) of the input, nrange entries
-    int nrange;
     float* smag;        // signed strength map (+M kept, -M suppressed) or NULL for
     int64_t spitch;     // the one-launch absolute path; pitch in floats, multiple of 4
     uint8_t* cls;
@@ -135,7 +133,6 @@ struct StageTimer {
     StageTimer& operator=(const StageTimer&) = delete;
 };
 
-constexpr int kF32RangeParts = 512;  // workgroups of the input min/max pass
 hipError_t launch_f32_forward(const F32FwdArgs& a, hipStream_t s);
 
 // ---------------------------------------------------------------- batches

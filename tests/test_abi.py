@@ -47,7 +47,7 @@ def test_status_strings_and_pitch(lib):
     assert lib.canny_status_string(0) == b"ok"
     assert lib.canny_status_string(2).startswith(b"workspace")
     assert lib.canny_status_string(99) == b"unknown status"
-    assert lib.canny_abi_version() == 2
+    assert lib.canny_abi_version() == 3
     for W, p in [(0, 0), (1, 4), (4, 4), (5, 4), (16, 4), (17, 8), (4096, 1024), (4097, 1028)]:
         assert lib.canny_class_pitch(W) == p, W
 

@@ -196,7 +196,7 @@ def test_float_stage_timing(canny):
         for _ in range(3):
             e, c = canny.canny_f32(dev, return_classes=True)
         torch.cuda.synchronize()
-        for stage in ("f32_minmax", "f32_walk", "f32_classify", "hysteresis"):
+        for stage in ("f32_clear", "f32_walk", "f32_classify", "hysteresis"):
             ms, n = t.read(stage)
             assert n == 3 and ms > 0.0, stage
         assert t.read("u8_forward") == (0.0, 0)
