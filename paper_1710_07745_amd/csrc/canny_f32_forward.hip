@@ -25,9 +25,10 @@
 //
 // Accuracy: every stage before the strength is linear, and Sobel ignores a
 // constant offset, so the walk filters X - c instead of X, with c the
-// midpoint of the value range of the wave's first input row.  On images whose
-// rows span the value range that halves the magnitude the fp32 accumulations
-// round at (never more than |X| itself), and a constant image gives exactly zero.
+// midpoint of the value range of the wave's first input row.  The fp32
+// accumulations then round at a magnitude no larger than the image's value
+// range (about half of it when that row spans the range), and a constant
+// image gives exactly zero.
 //
 // Suppression interpolates along the continuous gradient direction: with
 // t = min(|Gx|,|Gy|) / max(|Gx|,|Gy|) and same = (Gx*Gy > 0),
