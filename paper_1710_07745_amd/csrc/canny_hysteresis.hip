@@ -53,7 +53,13 @@ struct Tile {
 // an ancestor); used only while unions are running, before the root walks
 // that follow them, so a halving store can never overwrite a finished root
 // pointer
-__device__ __forceinline__ int lds_find_halve(volatile int* L, int x) {
+// Volatile views of LDS arrays keep the LDS address space: a volatile access
+// through a generic pointer compiles to a flat instruction (slower than an
+// LDS one, and it waits on the vector-memory counter as well).
+typedef __attribute__((address_space(3))) int lds_i32;
+__device__ __forceinline__ volatile lds_i32* lds_volatile(int* p) { return (volatile lds_i32*)p; }
+
+__device__ __forceinline__ int lds_find_halve(volatile lds_i32* L, int x) {
     for (int steps = x; steps >= 0; --steps) {  // pointers decrease: at most x + 1 hops
         const int p = L[x];
         if (p == x) return x;
@@ -66,7 +72,7 @@ __device__ __forceinline__ int lds_find_halve(volatile int* L, int x) {
 }
 
 __device__ __forceinline__ void lds_union(int* L, int a, int b) {
-    volatile int* V = L;
+    volatile lds_i32* V = lds_volatile(L);
     // each retry follows a link that strictly lowers a, so a + 1 rounds suffice
     for (int round = a > b ? a : b; round >= 0; --round) {
         a = lds_find_halve(V, a);
@@ -154,17 +160,20 @@ struct TileLabel {
 // cm holds the 64-bit candidate mask of every tile row.
 // Class codes (2 bits per pixel, pixel k at bits 2k) of 16 pixels of the
 // signed strength map: kept (value > 0) and > hi -> 2, kept and >= lo -> 1.
+// nquads >= 1: the four loads are unconditional (quads past nquads re-read
+// the last one and are masked), so all are in flight together.
 __device__ __forceinline__ uint32_t codes_from_signed(const float* row, int nquads, float lo, float hi) {
+    float4 v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = reinterpret_cast<const float4*>(row)[min(q, nquads - 1)];
     uint32_t codes = 0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        if (q >= nquads) break;
-        const float4 v = reinterpret_cast<const float4*>(row)[q];
-        const float e[4] = {v.x, v.y, v.z, v.w};
+        const float e[4] = {v[q].x, v[q].y, v[q].z, v[q].w};
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const uint32_t c = e[k] > 0.0f ? (e[k] > hi ? 2u : (e[k] >= lo ? 1u : 0u)) : 0u;
-            codes |= c << (2 * (4 * q + k));
+            codes |= (q < nquads ? c : 0u) << (2 * (4 * q + k));
         }
     }
     return codes;
@@ -188,7 +197,8 @@ __device__ __forceinline__ TileLabel<T> tile_label(const HystArgs& a, const Tile
             const float hi = a.relative ? a.high * mx : a.high;
             // whole quads that the row pitch holds from this segment on
             const int nq = (int)min((int64_t)4, max((int64_t)0, (a.spitch - (g.X0 + cb)) >> 2));
-            codes = codes_from_signed(a.smag + (int64_t)(g.Y0 + r) * a.spitch + g.X0 + cb, nq, lo, hi);
+            if (nq > 0)
+                codes = codes_from_signed(a.smag + (int64_t)(g.Y0 + r) * a.spitch + g.X0 + cb, nq, lo, hi);
         } else {
             const uint8_t* row = a.cls + (int64_t)(g.Y0 + r) * a.cpitch + ((g.X0 + cb) >> 2);
             const int avail = (int)(a.cpitch - ((g.X0 + cb) >> 2));  // bytes left in the row
@@ -241,7 +251,7 @@ __device__ __forceinline__ TileLabel<T> tile_label(const HystArgs& a, const Tile
     // decrease, so within i + 1 steps) and stores it.  Concurrent walks read
     // either an old pointer (an ancestor) or a root, so no store can mislead
     // another walk.
-    volatile int* V = L;
+    volatile lds_i32* V = lds_volatile(L);
     for (uint64_t b = Smine; b; b &= b - 1) {
         const int i = r * kHystCols + __ffsll((long long)b) - 1;
         int x = V[i];
