@@ -30,6 +30,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# non-packed fp32 VALU issue: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (lane-ops/s)
+VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 MALL_BYTES = 256 << 20
 
 
@@ -77,6 +79,19 @@ def bench_f32(canny, torch, H, W, steps, warmup, seed):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "f32_walk_4096_traffic.txt")
+VALU_FILE = os.path.join(ROOT, "profiles", "f32_walk_4096_valu.txt")
+
+
+def copy_bandwidth(torch, nbytes=1 << 30, reps=20):
+    """Device-to-device copy GB/s (bytes read + written) on the same GPU: what
+    a plain streaming kernel reaches, next to the 8 TB/s peak."""
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda").fill_(1)
+    dst = torch.empty_like(src)
+    st = torch.cuda.current_stream()
+    ms = timed(lambda: dst.copy_(src), reps, 3, st)
+    del src, dst
+    torch.cuda.empty_cache()
+    return round(2 * nbytes / (ms * 1e-3) / 1e9, 1)
 
 
 def roofline_headline(canny, torch, bufs, H, W, steps):
@@ -85,7 +100,7 @@ def roofline_headline(canny, torch, bufs, H, W, steps):
     same rotating buffers, after the timed one).  The dominant kernel is the
     float walk (Gaussian, Sobel, strength, suppression); its algorithmic bytes
     are the float forward's 4 B/px in + 0.25 B/px of class map out."""
-    from paper_1710_07745_amd.profiling import WALK_KERNEL, read_traffic
+    from paper_1710_07745_amd.profiling import WALK_KERNEL, read_traffic, read_valu
     xs, es, ws = bufs
     k = len(xs)
     with canny.StageTiming(steps) as t:
@@ -100,13 +115,17 @@ def roofline_headline(canny, torch, bufs, H, W, steps):
     walk_s = us["f32_walk"] * 1e-6
     gbs = alg / walk_s / 1e9
     fwd_s = (us["f32_clear"] + us["f32_walk"] + us["f32_classify"]) * 1e-6
+    valu_insts = read_valu(VALU_FILE)  # wave instructions per launch (x 64 lanes)
     return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": read_traffic(TRAFFIC_FILE),
             "kernel": WALK_KERNEL + " (float walk: blur, Sobel, strength, "
                       "suppression; 4096x4096)",
             "bytes_per_launch": alg, "avg_launch_us": us["f32_walk"],
             "stage_avg_us": us,
-            "forward_frac": round(alg / fwd_s / 1e9 / HBM_PEAK_GBS, 4)}
+            "forward_frac": round(alg / fwd_s / 1e9 / HBM_PEAK_GBS, 4),
+            "valu_insts_per_launch": valu_insts,
+            "valu_frac": None if valu_insts is None else
+            round(valu_insts * 64 / walk_s / VALU_PEAK_LANE_OPS, 4)}
 
 
 def bench_u8(canny, torch, img, steps, warmup, label):
@@ -265,6 +284,7 @@ def main():
     roof = roofline_headline(canny, torch, bufs, 4096, 4096, args.steps)
     del bufs
     torch.cuda.empty_cache()
+    roof["copy_gbs"] = copy_bandwidth(torch)
 
     configs = {}
     if not args.no_extra:

@@ -3,6 +3,9 @@
   python -m paper_1710_07745_amd.profiling stats DIR [--title T] [--command C]
       kernel table from DIR/*_kernel_stats.csv (rocprofv3 --kernel-trace
       --stats --output-format csv).
+  python -m paper_1710_07745_amd.profiling valu PMC_DIR [--kernel SUBSTR] [--command C ...]
+      VALU instructions (SQ_INSTS_VALU, per wave) and waves (SQ_WAVES) per
+      launch of the kernel, from one counter run (median over dispatches).
   python -m paper_1710_07745_amd.profiling traffic FETCH_DIR WRITE_DIR
       --kernel SUBSTR --copy-bytes N [--command C ...]
       HBM bytes per launch of the kernel whose name contains SUBSTR, from two
@@ -10,8 +13,8 @@
       Each counter is scaled by what it reads for the device copy kernel of
       N bytes in the same run (a copy fetches N and writes N bytes).
 
-The float walk's traffic line carries a hash of the kernel's sources; the
-benchmark reports that traffic only while the hash still matches.
+The float walk's traffic and VALU summaries carry a hash of the kernel's
+sources; the benchmark reports their figures only while the hash still matches.
 """
 from __future__ import annotations
 
@@ -38,9 +41,9 @@ def walk_source_hash() -> str:
     return h.hexdigest()
 
 
-def read_traffic(path: str):
-    """traffic_bytes_per_launch from a traffic summary, or None when the
-    file is missing or the walk's sources changed since it was taken."""
+def _read_field(path: str, field: str):
+    """A numeric field of a summary, or None when the file is missing or the
+    walk's sources changed since it was taken."""
     if not os.path.exists(path):
         return None
     kv = {}
@@ -51,9 +54,20 @@ def read_traffic(path: str):
     if kv.get("source_sha256") != walk_source_hash():
         return None
     try:
-        return float(kv["traffic_bytes_per_launch"])
+        return float(kv[field])
     except (KeyError, ValueError):
         return None
+
+
+def read_traffic(path: str):
+    """traffic_bytes_per_launch of a traffic summary (None if missing or stale)."""
+    return _read_field(path, "traffic_bytes_per_launch")
+
+
+def read_valu(path: str):
+    """valu_insts_per_launch (wave instructions) of a VALU summary (None if
+    missing or stale)."""
+    return _read_field(path, "valu_insts_per_launch")
 
 
 def _one(pattern: str) -> str:
@@ -119,6 +133,20 @@ def traffic(args) -> None:
         print(f"traffic_over_algorithmic: {total / args.alg_bytes:.3f}")
 
 
+def valu(args) -> None:
+    insts, n = _per_dispatch(args.dir, "SQ_INSTS_VALU", args.kernel)
+    waves, _ = _per_dispatch(args.dir, "SQ_WAVES", args.kernel)
+    print(f"# VALU instructions of {args.kernel} (hardware counters, per dispatch)")
+    for c in args.command or []:
+        print(f"# command: {c}")
+    print(f"kernel: {args.kernel}")
+    print(f"source_sha256: {walk_source_hash()}")
+    print(f"dispatches: {n}")
+    print(f"valu_insts_per_launch: {insts:.0f}")
+    print(f"waves_per_launch: {waves:.0f}")
+    print(f"valu_insts_per_wave: {insts / max(waves, 1):.1f}")
+
+
 def main(argv=None) -> None:
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -133,8 +161,12 @@ def main(argv=None) -> None:
     t.add_argument("--copy-bytes", type=float, required=True)
     t.add_argument("--alg-bytes", type=float, default=0.0)
     t.add_argument("--command", action="append")
+    v = sub.add_parser("valu")
+    v.add_argument("dir")
+    v.add_argument("--kernel", default=WALK_KERNEL)
+    v.add_argument("--command", action="append")
     a = ap.parse_args(argv)
-    stats(a) if a.cmd == "stats" else traffic(a)
+    {"stats": stats, "traffic": traffic, "valu": valu}[a.cmd](a)
 
 
 if __name__ == "__main__":

@@ -51,3 +51,21 @@ def test_committed_traffic_summary_parses():
     path = os.path.join(profiling.ROOT, "profiles", "f32_walk_4096_traffic.txt")
     kv = dict(ln.split(":", 1) for ln in open(path) if ":" in ln and not ln.startswith("#"))
     assert float(kv["traffic_bytes_per_launch"]) > float(kv["algorithmic_bytes_per_launch"]) > 0
+
+
+def test_valu_summary(tmp_path, capsys):
+    d = str(tmp_path / "v")
+    write_counters(d, [["k_walk<3>(args)", "SQ_INSTS_VALU", 9000.0],
+                       ["k_walk<3>(args)", "SQ_INSTS_VALU", 8000.0],
+                       ["k_walk<3>(args)", "SQ_INSTS_VALU", 8500.0],
+                       ["k_walk<3>(args)", "SQ_WAVES", 10.0],
+                       ["other", "SQ_INSTS_VALU", 1.0]])
+    profiling.main(["valu", d, "--kernel", "k_walk<3>"])
+    out = dict(ln.split(":", 1) for ln in capsys.readouterr().out.splitlines() if not ln.startswith("#"))
+    assert float(out["valu_insts_per_launch"]) == 8500.0
+    assert float(out["valu_insts_per_wave"]) == 850.0
+    p = tmp_path / "valu.txt"
+    p.write_text("\n".join(f"{k}:{v}" for k, v in out.items()) + "\n")
+    assert profiling.read_valu(str(p)) == 8500.0
+    p.write_text("source_sha256: 0\nvalu_insts_per_launch: 8500\n")
+    assert profiling.read_valu(str(p)) is None
