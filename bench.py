@@ -241,6 +241,45 @@ def cpu_baseline(seconds=10.0):
                       f"benchmark image, {dt:.1f} s"}
 
 
+def cpu_paper_design(reps=3):
+    """The float operator on the host in the paper's own design: Steps 1-3 as
+    row-parallel loops, hysteresis serial (oracle/paper_design.c).  Measures
+    the parallel fraction f at one thread and the speedup on all threads the
+    box grants, and evaluates Amdahl's law and the paper's asymmetric-multicore
+    form 1 / ((1-f)/perf(r) + f/(perf(r)+n-r)) with perf(r) = sqrt(r) (the
+    paper does not define perf; sqrt is the usual assumption for that form)."""
+    import math
+    import numpy as np
+    import oracle
+    import workloads
+    X = workloads.natural_u8(4096, 4096, seed=1).astype(np.float32)
+    n = max(1, min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS", "16") or 16)))
+    oracle.paper_design_canny_f32(X, n)  # page in
+
+    def best(threads, k):
+        runs = [oracle.paper_design_canny_f32(X, threads)[1:] for _ in range(k)]
+        return min(runs, key=lambda t: t[0] + t[1])
+
+    p1, s1 = best(1, 1)
+    pn, sn = best(n, reps)
+    f = p1 / (p1 + s1)
+    asym = {}
+    for r in (1, 4, 16):
+        if r <= n:
+            perf = math.sqrt(r)
+            asym[f"r{r}"] = round(1.0 / ((1.0 - f) / perf + f / (perf + n - r)), 2)
+    return {"unit": "MPix/s", "threads": n, "image": "4096x4096 float, sigma 1.4, radius 3, "
+            "relative thresholds 0.05/0.15 (the headline workload)",
+            "mpix_s_1thread": round(4096 * 4096 / (p1 + s1) / 1e6, 2),
+            "mpix_s": round(4096 * 4096 / (pn + sn) / 1e6, 2),
+            "ms_parallel_part": [round(p1 * 1e3, 1), round(pn * 1e3, 1)],
+            "ms_serial_part": [round(s1 * 1e3, 1), round(sn * 1e3, 1)],
+            "parallel_fraction_f": round(f, 4),
+            "speedup_measured": round((p1 + s1) / (pn + sn), 2),
+            "speedup_amdahl": round(1.0 / ((1.0 - f) + f / n), 2),
+            "speedup_asymmetric_sqrt_perf": asym}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -309,6 +348,10 @@ def main():
                 configs[name] = f(canny, torch, args.steps, args.warmup)
 
     cpu = None if args.no_cpu else cpu_baseline()
+    cpu_pd = None
+    if cpu is not None:
+        log("cpu paper-design baseline")
+        cpu_pd = cpu_paper_design()
     line = {
         "metric": "Canny MPix/s at 4096² & batched uneven sizes; % HBM roofline; fwd+bwd MPix/s",
         "value": round(head["mpix_s"], 1),
@@ -327,6 +370,7 @@ def main():
                    "image": [4096, 4096], "rotating_buffers": head["rot_buffers"]},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "cpu_paper_design": cpu_pd,
         "configs": configs,
     }
     print(json.dumps(line), flush=True)

@@ -9,6 +9,10 @@ This is a thin ctypes wrapper around ``canny_oracle.c`` (plain C, fp64 for all
 floating point), plus ``build()`` which compiles it with gcc.  Every function
 cites the step of the paper (Section 2.2.1, Steps 1-4) it follows; the C file
 carries the definitions.
+
+``paper_design_canny_f32`` wraps ``paper_design.c``: the same float operator
+in the paper's parallel design (row-parallel Steps 1-3, serial hysteresis,
+OpenMP), a measured CPU baseline for the benchmark, not an oracle.
 """
 from __future__ import annotations
 
@@ -21,7 +25,10 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "canny_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+_PD_SRC = os.path.join(_HERE, "paper_design.c")
+_PD_LIB = os.path.join(_HERE, "libpaper_design.so")
 _lib = None
+_pd_lib = None
 
 
 def build(force: bool = True) -> str:
@@ -31,6 +38,11 @@ def build(force: bool = True) -> str:
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-shared", "-fPIC",
                                "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
+    if force or not os.path.exists(_PD_LIB):
+        tmp = _PD_LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fopenmp", "-shared",
+                               "-fPIC", "-o", tmp, _PD_SRC, _SRC, "-lm"])
+        os.replace(tmp, _PD_LIB)
     return _LIB
 
 
@@ -207,3 +219,35 @@ def mag_backward(I, sigma, gM, R=9):
     ds = C.c_double(0.0)
     _load().oracle_mag_backward(_p(I), H, W, float(sigma), int(R), _p(gM), _p(dI), C.byref(ds))
     return dI, ds.value
+
+
+# ---- the paper's parallel design on the CPU (baseline, not an oracle) ------
+
+def _load_pd():
+    global _pd_lib
+    if _pd_lib is not None:
+        return _pd_lib
+    if (not os.path.exists(_PD_LIB) or os.path.getmtime(_PD_LIB) < os.path.getmtime(_PD_SRC)
+            or os.path.getmtime(_PD_LIB) < os.path.getmtime(_SRC)):
+        build()
+    lib = C.CDLL(_PD_LIB)
+    lib.pd_canny_f32.restype = C.c_int
+    lib.pd_canny_f32.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_double, C.c_int, C.c_double,
+                                 C.c_double, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]
+    _pd_lib = lib
+    return lib
+
+
+def paper_design_canny_f32(X, nthreads, sigma=1.4, R=3, low=0.05, high=0.15, relative=True):
+    """Float Canny with row-parallel Steps 1-3 on ``nthreads`` threads and
+    serial hysteresis.  Returns (edges, seconds parallel part, seconds serial part)."""
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    H, W = X.shape
+    edges = np.empty((H, W), np.uint8)
+    tp, ts = C.c_double(0.0), C.c_double(0.0)
+    rc = _load_pd().pd_canny_f32(_p(X), H, W, float(sigma), int(R), float(low), float(high),
+                                 int(bool(relative)), int(nthreads), _p(edges), C.byref(tp),
+                                 C.byref(ts))
+    if rc != 0:
+        raise MemoryError("paper-design baseline: allocation failed")
+    return edges, tp.value, ts.value
