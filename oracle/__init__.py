@@ -68,6 +68,8 @@ def _load():
         "oracle_gauss_blur": (None, [P, i, i, d, i, P]),
         "oracle_sobel_f64": (None, [P, i, i, P, P]),
         "oracle_classify_f32": (l, [P, i, i, d, i, d, d, i, d, P, P, P, P]),
+        "oracle_sector_f64": (i, [d, d]),
+        "oracle_classify_f32_sector": (l, [P, i, i, d, i, d, d, i, d, P, P, P, P]),
         "oracle_mag_forward": (None, [P, i, i, d, i, P]),
         "oracle_mag_backward": (None, [P, i, i, d, i, P, P, P]),
     }
@@ -191,6 +193,26 @@ def classify_f32(X, sigma=1.4, R=3, low=0.05, high=0.15, relative=True, tol=1e-5
     _load().oracle_classify_f32(_p(X), H, W, float(sigma), int(R), float(low), float(high),
                                 int(bool(relative)), float(tol), _p(cls), _p(M), _p(amb),
                                 C.byref(mx))
+    return cls, M, amb, mx.value
+
+
+def sector_f64(gx, gy):
+    """Four-sector code of a float gradient (Section 2.2.1, Step 2 direction)."""
+    return _load().oracle_sector_f64(float(gx), float(gy))
+
+
+def classify_f32_sector(X, sigma=1.4, R=3, low=20.0, high=60.0, relative=False, tol=1e-5):
+    """Float path with the four-sector direction (Step 3 against p -/+ d).
+    Returns (class map, M fp64, ambiguity bit flags (bits 0, 1, 3), max M)."""
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    H, W = X.shape
+    cls = np.empty((H, W), np.uint8)
+    M = np.empty((H, W), np.float64)
+    amb = np.empty((H, W), np.uint8)
+    mx = C.c_double(0.0)
+    _load().oracle_classify_f32_sector(_p(X), H, W, float(sigma), int(R), float(low), float(high),
+                                       int(bool(relative)), float(tol), _p(cls), _p(M), _p(amb),
+                                       C.byref(mx))
     return cls, M, amb, mx.value
 
 

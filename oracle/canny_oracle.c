@@ -360,6 +360,79 @@ long oracle_classify_f32(const float* X, int H, int W, double sigma, int R, doub
     return namb;
 }
 
+/* Gradient direction of the float path quantised to four sectors, as in
+ * the integer path (the nearest multiple of 45 degrees of atan2(Gy, Gx)
+ * modulo 180; Algorithm 1 forms an explicit direction angle), codes as in
+ * oracle_sector.  Used by the four-sector variant below. */
+int oracle_sector_f64(double gx, double gy) {
+    double th = atan2(gy, gx) * (180.0 / M_PI);
+    if (th < 0.0) th += 180.0;
+    int q = (int)floor(th / 45.0 + 0.5);
+    return q & 3;
+}
+
+/* Steps 1-3 and the double threshold, float path with the four-sector
+ * direction: Gaussian, Sobel and L2 strength exactly as in
+ * oracle_classify_f32, then suppression against the two 8-neighbours
+ * p - d and p + d along the quantised direction d (clamped reads): keep iff
+ * M > 0, M > M(p - d) and M >= M(p + d) (the raster tie rule of the integer
+ * path).  Thresholds as in oracle_classify_f32.  amb bit flags:
+ *   bit 0: within tol of a threshold, bit 1: suppression near-tie,
+ *   bit 3: direction near a sector boundary, |ay - k ax| <= 4 tol M for
+ *          k = tan(22.5 deg) or tan(67.5 deg) (an fp32 evaluation of the
+ *          boundary test can land on either side there), or M = 0.
+ * Returns the number of pixels with bit 0, 1 or 3 set. */
+long oracle_classify_f32_sector(const float* X, int H, int W, double sigma, int R, double low,
+                                double high, int relative, double tol, uint8_t* cls,
+                                double* M_out, uint8_t* amb, double* mx_out) {
+    long n = (long)H * W;
+    double* Xd = (double*)malloc(n * sizeof(double));
+    double* B = (double*)malloc(n * sizeof(double));
+    double* Gx = (double*)malloc(n * sizeof(double));
+    double* Gy = (double*)malloc(n * sizeof(double));
+    double* M = (double*)malloc(n * sizeof(double));
+    for (long k = 0; k < n; ++k) Xd[k] = (double)X[k];
+    oracle_gauss_blur(Xd, H, W, sigma, R, B);
+    oracle_sobel_f64(B, H, W, Gx, Gy);
+    double mx = 0.0;
+    for (long k = 0; k < n; ++k) {
+        M[k] = sqrt(Gx[k] * Gx[k] + Gy[k] * Gy[k]);
+        if (M[k] > mx) mx = M[k];
+    }
+    double lo = relative ? low * mx : low;
+    double hi = relative ? high * mx : high;
+    const double k1 = sqrt(2.0) - 1.0, k2 = sqrt(2.0) + 1.0;
+    long namb = 0;
+    for (int y = 0; y < H; ++y) {
+        for (int x = 0; x < W; ++x) {
+            long k = (long)y * W + x;
+            int sec = oracle_sector_f64(Gx[k], Gy[k]);
+            int dy = kSecDy[sec], dx = kSecDx[sec];
+            double mb = Mat(M, H, W, y - dy, x - dx);
+            double mf = Mat(M, H, W, y + dy, x + dx);
+            int keep = (M[k] > 0.0) && (M[k] > mb) && (M[k] >= mf);
+            uint8_t c = 0;
+            if (keep && M[k] > hi) c = 2;
+            else if (keep && M[k] >= lo) c = 1;
+            cls[k] = c;
+            if (amb) {
+                double m = M[k], ax = fabs(Gx[k]), ay = fabs(Gy[k]);
+                int a = 0;
+                if (fabs(m - lo) <= tol * lo || fabs(m - hi) <= tol * hi) a |= 1;
+                if (m > 0.0 && (fabs(m - mb) <= tol * m || fabs(m - mf) <= tol * m)) a |= 2;
+                if (m == 0.0 || fabs(ay - k1 * ax) <= 4.0 * tol * m || fabs(ay - k2 * ax) <= 4.0 * tol * m)
+                    a |= 8;
+                amb[k] = (uint8_t)a;
+                namb += (a & 11) != 0;
+            }
+        }
+    }
+    if (M_out) memcpy(M_out, M, n * sizeof(double));
+    if (mx_out) *mx_out = mx;
+    free(Xd); free(B); free(Gx); free(Gy); free(M);
+    return namb;
+}
+
 /* ------------------------------------------------------------------------
  * Differentiable front end M(I, sigma) = |Sobel * G_sigma * I| (L2 norm)
  * ---------------------------------------------------------------------- */

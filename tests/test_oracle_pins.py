@@ -366,6 +366,62 @@ def test_float_constant_and_ramp():
     assert np.all(amb[inner] & 2)
 
 
+# ------------------------------------------------- float, four-sector direction
+
+def test_sector_f64_equals_integer_sector():
+    """The float sector code agrees with the integer one (itself pinned
+    exhaustively against the exact squared tests) on every integer gradient."""
+    r = np.arange(-60, 61)
+    for gx in r:
+        for gy in r:
+            if gx == 0 and gy == 0:
+                continue
+            assert oracle.sector_f64(float(gx), float(gy)) == oracle.sector(int(gx), int(gy))
+
+
+@pytest.mark.parametrize("transpose", [False, True])
+def test_sector_equals_interpolation_on_axis_aligned_steps(transpose):
+    """Gradients along an axis (t = 0): the interpolated neighbours are the
+    axis neighbours, so both suppression rules decide every pixel alike."""
+    X = np.full((48, 56), 40.0, np.float32)
+    X[:, 25] = 90.0
+    X[:, 26:] = 170.0
+    X[:, 40:] = 120.0
+    if transpose:
+        X = np.ascontiguousarray(X.T)
+    a, _, _, _ = oracle.classify_f32(X, 1.4, 3, 5.0, 20.0, False)
+    b, _, _, _ = oracle.classify_f32_sector(X, 1.4, 3, 5.0, 20.0, False)
+    assert (a > 0).sum() > 40
+    assert np.array_equal(a, b)
+
+
+def test_sector_equals_interpolation_on_diagonal_step():
+    """I(y, x) = f(x + y): away from the border Gx = Gy exactly (t = 1), so the
+    interpolated neighbours are the (1, 1) diagonal ones, the sector rule's."""
+    y, x = np.mgrid[0:64, 0:64]
+    s = x + y
+    X = np.where(s < 60, 30.0, np.where(s == 60, 100.0, 200.0)).astype(np.float32)
+    a, _, _, _ = oracle.classify_f32(X, 1.4, 3, 5.0, 20.0, False)
+    b, _, _, _ = oracle.classify_f32_sector(X, 1.4, 3, 5.0, 20.0, False)
+    inner = np.s_[6:-6, 6:-6]
+    assert (a[inner] > 0).sum() > 20
+    assert np.array_equal(a[inner], b[inner])
+
+
+def test_sector_variant_constant_and_flags():
+    cls, M, amb, mx = oracle.classify_f32_sector(np.full((20, 30), 3.0, np.float32))
+    assert not cls.any() and mx == 0.0 and np.all(amb & 8)  # M = 0 everywhere
+    X = workloads.natural_u8(80, 120, seed=5).astype(np.float32)
+    cls, M, amb, mx = oracle.classify_f32_sector(X, 1.4, 3, 0.05, 0.15, True)
+    gx, gy = oracle.sobel_f64(oracle.gauss_blur(X.astype(np.float64), 1.4, 3))
+    # bit 3 marks exactly the gradients near the 22.5 / 67.5 degree boundaries
+    ax, ay = np.abs(gx), np.abs(gy)
+    near = (M == 0) | (np.abs(ay - (np.sqrt(2) - 1) * ax) <= 4e-5 * M) | \
+        (np.abs(ay - (np.sqrt(2) + 1) * ax) <= 4e-5 * M)
+    assert np.array_equal((amb & 8) != 0, near)
+    assert (cls == 2).sum() > 0 and (cls == 1).sum() > 0
+
+
 # ---------------------------------------------------------------- differentiable
 
 def _torch_mag(I, sigma, R):
