@@ -58,7 +58,7 @@ def n_rot(bytes_per_set):
     return max(2, -(-2 * MALL_BYTES // max(bytes_per_set, 1)))
 
 
-def bench_f32(canny, torch, H, W, steps, warmup, seed):
+def bench_f32(canny, torch, H, W, steps, warmup, seed, sector=False):
     import numpy as np
     import workloads
     X = workloads.natural_u8(H, W, seed=seed).astype(np.float32)
@@ -71,7 +71,10 @@ def bench_f32(canny, torch, H, W, steps, warmup, seed):
     def step():
         i = it[0] % k
         it[0] += 1
-        canny.canny_f32(xs[i], 1.4, 3, 0.05, 0.15, True, edges=es[i], workspace=ws)
+        if sector:  # four-sector direction, absolute thresholds near 0.05 / 0.15 of the max
+            canny.canny_f32_sector(xs[i], 1.4, 3, 16.0, 48.0, edges=es[i], workspace=ws)
+        else:
+            canny.canny_f32(xs[i], 1.4, 3, 0.05, 0.15, True, edges=es[i], workspace=ws)
 
     st = torch.cuda.current_stream()
     ms = timed(step, steps, warmup, st)
@@ -337,6 +340,13 @@ def main():
         torch.cuda.empty_cache()
         configs["f32_7680x4320"] = {"workload": "float Canny, 7680x4320 fp32",
                                     "ms": round(r["ms"], 4), "mpix_s": round(r["mpix_s"], 1)}
+        log("f32 four-sector 4096x4096")
+        r, b = bench_f32(canny, torch, 4096, 4096, args.steps, args.warmup, seed=1, sector=True)
+        del b
+        torch.cuda.empty_cache()
+        configs["f32_sector_4096"] = {"workload": "float Canny, four-sector direction, absolute "
+                                                  "thresholds 16/48, 4096x4096 fp32",
+                                      "ms": round(r["ms"], 4), "mpix_s": round(r["mpix_s"], 1)}
         log("u8 16384x16384 spiral")
         configs["u8_16384_spiral"] = bench_u8(canny, torch, workloads.spiral_u8(16384, seed=5),
                                               max(3, args.steps // 5), 2,

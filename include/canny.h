@@ -136,6 +136,23 @@ int canny_f32(const float* in, int64_t in_pitch, int H, int W, float sigma, int 
               void* stream);
 
 /* ---------------------------------------------------------------------
+ * Float Canny with the four-sector direction (Steps 1-4, fp32).
+ *
+ * As canny_f32 with absolute thresholds, except Step 3: the gradient
+ * direction is quantised to the nearest multiple of 45 degrees (Algorithm 1
+ * forms an explicit direction angle; the four sectors are those of the
+ * integer path: |Gy| < tan(22.5) |Gx| -> x axis, |Gy| > tan(67.5) |Gx| ->
+ * y axis, otherwise the diagonal (1, 1) when Gx and Gy share a sign, else
+ * (1, -1)), and M is kept iff M > 0, M > M(p - d) and M >= M(p + d) with
+ * clamped neighbours.  One kernel classifies; then hysteresis.
+ * Arguments, layouts, ownership and errors as canny_f32 (low/high are
+ * absolute strengths; there is no largest-strength output).
+ */
+int canny_f32_sector(const float* in, int64_t in_pitch, int H, int W, float sigma, int radius,
+                     float low, float high, uint8_t* edges, int64_t edges_pitch, uint8_t* class2,
+                     float* mag_out, void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------
  * Batched integer Canny over many images of uneven sizes.
  *
  * The same operator as canny_u8, applied to n independent images.  The

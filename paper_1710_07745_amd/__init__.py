@@ -20,7 +20,7 @@ from . import _lib
 from ._lib import CannyError, check, lib
 
 __all__ = [
-    "canny_u8", "canny_f32", "hysteresis", "class_pitch", "u8_workspace_bytes", "f32_workspace_bytes",
+    "canny_u8", "canny_f32", "canny_f32_sector", "hysteresis", "class_pitch", "u8_workspace_bytes", "f32_workspace_bytes",
     "BatchPlan", "mag_forward", "mag_backward", "CannyMagnitude", "canny_magnitude",
     "CannyError", "StageTiming",
 ]
@@ -132,6 +132,34 @@ def canny_f32(img: torch.Tensor, sigma: float = 1.4, radius: int = 3, low: float
         out.append(mag)
     if return_max:
         out.append(mx)
+    return out[0] if len(out) == 1 else tuple(out)
+
+
+def canny_f32_sector(img: torch.Tensor, sigma: float = 1.4, radius: int = 3, low: float = 20.0,
+                     high: float = 60.0, *, edges: Optional[torch.Tensor] = None,
+                     with_edges: bool = True, return_classes: bool = False,
+                     return_magnitude: bool = False, workspace: Optional[torch.Tensor] = None):
+    """Float Canny with the direction quantised to four sectors (suppression
+    against the two 8-neighbours along it) and absolute thresholds.  Returns
+    edges, then optionally the class map and the fp32 strength map."""
+    _check_image(img, torch.float32)
+    H, W = img.shape
+    dev = img.device
+    if with_edges and edges is None:
+        edges = torch.empty((H, W), dtype=torch.uint8, device=dev)
+    cls = torch.empty((H, class_pitch(W)), dtype=torch.uint8, device=dev) if return_classes else None
+    mag = torch.empty((H, W), dtype=torch.float32, device=dev) if return_magnitude else None
+    ws = _workspace(f32_workspace_bytes(H, W), dev, workspace)
+    st = lib().canny_f32_sector(img.data_ptr(), img.stride(0), H, W, float(sigma), int(radius),
+                                float(low), float(high), _ptr(edges) if with_edges else None,
+                                edges.stride(0) if with_edges else 0, _ptr(cls), _ptr(mag),
+                                ws.data_ptr(), ws.numel() * ws.element_size(), _stream(img))
+    check("canny_f32_sector", st)
+    out = [edges if with_edges else None]
+    if return_classes:
+        out.append(cls)
+    if return_magnitude:
+        out.append(mag)
     return out[0] if len(out) == 1 else tuple(out)
 
 

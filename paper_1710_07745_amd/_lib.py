@@ -36,6 +36,8 @@ SIGNATURES = {
     "canny_f32_workspace_bytes": (sz, [C.c_int, C.c_int]),
     "canny_f32": (C.c_int, [P, i64, C.c_int, C.c_int, f32, C.c_int, f32, f32, C.c_int, P, i64, P,
                             P, P, P, sz, P]),
+    "canny_f32_sector": (C.c_int, [P, i64, C.c_int, C.c_int, f32, C.c_int, f32, f32, P, i64, P, P,
+                                   P, sz, P]),
     "canny_batch_plan_create": (C.c_int, [C.c_int, P, P, i32, i32, C.c_int, C.POINTER(P)]),
     "canny_batch_workspace_bytes": (sz, [P]),
     "canny_batch": (C.c_int, [P, P, P, P, P, P, sz, P]),

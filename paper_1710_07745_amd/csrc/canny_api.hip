@@ -74,7 +74,7 @@ const char* canny_status_string(int status) {
     }
 }
 
-int canny_abi_version(void) { return 3; }
+int canny_abi_version(void) { return 4; }
 
 int64_t canny_class_pitch(int W) { return class_pitch(W); }
 
@@ -161,9 +161,10 @@ size_t canny_f32_workspace_bytes(int H, int W) {
            align256((size_t)H * smag_pitch(W) * 4);
 }
 
-int canny_f32(const float* in, int64_t in_pitch, int H, int W, float sigma, int radius, float low,
-              float high, int relative, uint8_t* edges, int64_t edges_pitch, uint8_t* class2,
-              float* mag_out, float* max_out, void* ws, size_t ws_bytes, void* stream) {
+static int f32_impl(const float* in, int64_t in_pitch, int H, int W, float sigma, int radius,
+                    float low, float high, int relative, uint8_t* edges, int64_t edges_pitch,
+                    uint8_t* class2, float* mag_out, float* max_out, void* ws, size_t ws_bytes,
+                    void* stream, int sector) {
     if (!in || !size_ok(H, W) || in_pitch < W) return CANNY_ERR_INVALID;
     if (!(sigma > 0.0f) || !std::isfinite(sigma) || radius < 1 || radius > 8) return CANNY_ERR_INVALID;
     if (!(low >= 0.0f) || !(high >= low) || !std::isfinite(high)) return CANNY_ERR_INVALID;
@@ -212,6 +213,7 @@ int canny_f32(const float* in, int64_t in_pitch, int H, int W, float sigma, int 
     // hysteresis pass classifies straight from the signed map: no class map.
     const bool fused = f.smag && !class2 && !mag_out && edges;
     f.skip_classify = fused ? 1 : 0;
+    f.sector = sector;
     hipError_t e = launch_f32_forward(f, s);
     if (e != hipSuccess || !edges) return status_of(e);
     HystArgs h;
@@ -233,6 +235,21 @@ int canny_f32(const float* in, int64_t in_pitch, int H, int W, float sigma, int 
     const int T = hyst_tile_rows_default();
     hyst_carve(w + hyst_off, H, W, T, h);
     return status_of(timed_hysteresis(h, T, s));
+}
+
+int canny_f32(const float* in, int64_t in_pitch, int H, int W, float sigma, int radius, float low,
+              float high, int relative, uint8_t* edges, int64_t edges_pitch, uint8_t* class2,
+              float* mag_out, float* max_out, void* ws, size_t ws_bytes, void* stream) {
+    return f32_impl(in, in_pitch, H, W, sigma, radius, low, high, relative, edges, edges_pitch,
+                    class2, mag_out, max_out, ws, ws_bytes, stream, 0);
+}
+
+int canny_f32_sector(const float* in, int64_t in_pitch, int H, int W, float sigma, int radius,
+                     float low, float high, uint8_t* edges, int64_t edges_pitch, uint8_t* class2,
+                     float* mag_out, void* ws, size_t ws_bytes, void* stream) {
+    // absolute thresholds and no largest-strength output: the walk classifies
+    return f32_impl(in, in_pitch, H, W, sigma, radius, low, high, 0, edges, edges_pitch, class2,
+                    mag_out, nullptr, ws, ws_bytes, stream, 1);
 }
 
 static bool mag_args_ok(const float* I, const float* sigma, int N, int H, int W, int radius) {

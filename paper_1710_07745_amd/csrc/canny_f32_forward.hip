@@ -39,6 +39,10 @@
 // which is the 3x3-ring interpolation where the gradient line leaves the
 // neighbourhood, written with the forward side fixed to the positive step of
 // the dominant axis.
+//
+// SECTOR = true (one-launch mode only) is the variant with the direction
+// quantised to the nearest multiple of 45 degrees, as in the integer path:
+// suppression compares M with the two 8-neighbours p - d and p + d along it.
 #include "../../include/canny.h"
 #include "canny_internal.h"
 #include "canny_f32_common.h"
@@ -102,8 +106,9 @@ struct WalkPlan {
     int k, nb;           // interior / bottom border blocks per interior strip
 };
 
-template <int R, int RR, bool SIGNED, bool EDGE>
+template <int R, int RR, bool SIGNED, bool SECTOR, bool EDGE>
 __device__ __forceinline__ void f32_walk(const F32FwdArgs& a, int X0, int Y0, int lane, int fast_ok) {
+    static_assert(!(SIGNED && SECTOR), "the four-sector variant classifies in the walk");
     constexpr int HL = WalkShape<R>::HL;
     constexpr int HR = WalkShape<R>::HR;
     constexpr int NI = RR + 2 * HR;          // input rows
@@ -217,7 +222,20 @@ __device__ __forceinline__ void f32_walk(const F32FwdArgs& a, int X0, int Y0, in
                     const float ahead = fmaf(mn, fd - fp, fp * mxv);
                     const float behind = fmaf(mn, bdg - bp, bp * mxv);
                     const float ms = mc * mxv;
-                    const bool keep = mc > 0.0f && ms > behind && ms >= ahead;
+                    bool keep = mc > 0.0f && ms > behind && ms >= ahead;
+                    if (SECTOR) {
+                        // four-sector direction (nearest multiple of 45 degrees):
+                        // axis x if ay < tan(22.5) ax, axis y if ay > tan(67.5) ax,
+                        // else the diagonal (1, 1) (Gx, Gy of one sign) or (1, -1);
+                        // compare with p - d (strictly) and p + d
+                        const bool on_x = ay < 0.41421356f * ax, on_y = ay > 2.41421356f * ax;
+                        float back = same ? ul : ur, fwd = same ? dr : dl;
+                        back = on_y ? uc : back;
+                        fwd = on_y ? dc : fwd;
+                        back = on_x ? cl : back;
+                        fwd = on_x ? cr : fwd;
+                        keep = mc > 0.0f && mc > back && mc >= fwd;
+                    }
                     if (SIGNED) {
                         // two selects on compare results instead of one on their
                         // conjunction (no scalar mask arithmetic between vector ops);
@@ -338,7 +356,7 @@ __device__ __forceinline__ void f32_walk(const F32FwdArgs& a, int X0, int Y0, in
 
 // At least 3 waves per SIMD (<= 168 VGPRs); radii >= 6 need a longer input
 // window and are allowed 2 (<= 256 VGPRs) rather than spill.
-template <int R, int RR, bool SIGNED>
+template <int R, int RR, bool SIGNED, bool SECTOR>
 __global__ void __launch_bounds__(kWGThreads) __attribute__((amdgpu_waves_per_eu(R >= 6 ? 2 : 3)))
 k_f32_forward(F32FwdArgs a, int strips_x, int nwaves, int fast_ok) {
     constexpr int HL = WalkShape<R>::HL;
@@ -356,15 +374,15 @@ k_f32_forward(F32FwdArgs a, int strips_x, int nwaves, int fast_ok) {
     const bool interior = fast_ok && X0 - 4 * HL >= 0 && X0 + SC + 4 * HL <= a.W &&
                           Y0 - HR >= 0 && Y0 + RR + HR <= a.H;
     if (interior)
-        f32_walk<R, RR, SIGNED, false>(a, X0, Y0, lane, fast_ok);
+        f32_walk<R, RR, SIGNED, SECTOR, false>(a, X0, Y0, lane, fast_ok);
     else
-        f32_walk<R, RR, SIGNED, true>(a, X0, Y0, lane, fast_ok);
+        f32_walk<R, RR, SIGNED, SECTOR, true>(a, X0, Y0, lane, fast_ok);
 }
 
 // Balanced launch: interior blocks of RRI rows, border blocks of RRE rows
 // (see WalkPlan).  The task decides the variant; the interior conditions hold
 // by construction and are checked again before the unclamped walk.
-template <int R, int RRI, int RRE, bool SIGNED>
+template <int R, int RRI, int RRE, bool SIGNED, bool SECTOR>
 __global__ void __launch_bounds__(kWGThreads) __attribute__((amdgpu_waves_per_eu(R >= 6 ? 2 : 3)))
 k_f32_forward_bal(F32FwdArgs a, WalkPlan p, int fast_ok) {
     constexpr int HL = WalkShape<R>::HL;
@@ -399,9 +417,9 @@ k_f32_forward_bal(F32FwdArgs a, WalkPlan p, int fast_ok) {
         if (!(fast_ok && X0 - 4 * HL >= 0 && X0 + SC + 4 * HL <= a.W && Y0 - HR >= 0 &&
               Y0 + RRI + HR <= a.H))
             return;  // unreachable for a plan from make_walk_plan
-        f32_walk<R, RRI, SIGNED, false>(a, X0, Y0, lane, fast_ok);
+        f32_walk<R, RRI, SIGNED, SECTOR, false>(a, X0, Y0, lane, fast_ok);
     } else {
-        f32_walk<R, RRE, SIGNED, true>(a, X0, Y0, lane, fast_ok);
+        f32_walk<R, RRE, SIGNED, SECTOR, true>(a, X0, Y0, lane, fast_ok);
     }
 }
 
@@ -476,12 +494,12 @@ k_f32_classify(F32FwdArgs a) {
 int rows_grid(int H) { return min(H, 512); }
 
 // One walk launch with RR output rows per wave.
-template <int R, int RR, bool SIGNED>
+template <int R, int RR, bool SIGNED, bool SECTOR>
 void launch_walk(const F32FwdArgs& a, int fast_ok, hipStream_t s) {
     const int strips_x = ceil_div(a.W, WalkShape<R>::SC);
     const int nwaves = strips_x * ceil_div(a.H, RR);
     const int nwg = ceil_div(nwaves, kWavesPerWG);
-    hipLaunchKernelGGL((k_f32_forward<R, RR, SIGNED>), dim3(nwg), dim3(kWGThreads), 0, s, a,
+    hipLaunchKernelGGL((k_f32_forward<R, RR, SIGNED, SECTOR>), dim3(nwg), dim3(kWGThreads), 0, s, a,
                        strips_x, nwaves, fast_ok);
 }
 
@@ -517,14 +535,14 @@ WalkPlan make_walk_plan(int H, int W, int fast_ok) {
 // images (halo rows amortised) and short ones small images (more waves in
 // flight).  The balanced split unless that leaves fewer than 1024 waves (one
 // per SIMD); then 8 rows per wave.
-template <int R, bool SIGNED>
+template <int R, bool SIGNED, bool SECTOR = false>
 void launch_walk_sized(const F32FwdArgs& a, int fast_ok, hipStream_t s) {
     const WalkPlan p = make_walk_plan<R>(a.H, a.W, fast_ok);
     if (p.nwaves >= 1024) {
-        hipLaunchKernelGGL((k_f32_forward_bal<R, kRRI, kRRE, SIGNED>), dim3(ceil_div(p.nwaves, kWavesPerWG)),
+        hipLaunchKernelGGL((k_f32_forward_bal<R, kRRI, kRRE, SIGNED, SECTOR>), dim3(ceil_div(p.nwaves, kWavesPerWG)),
                            dim3(kWGThreads), 0, s, a, p, fast_ok);
     } else {
-        launch_walk<R, 8, SIGNED>(a, fast_ok, s);
+        launch_walk<R, 8, SIGNED, SECTOR>(a, fast_ok, s);
     }
 }
 
@@ -533,7 +551,10 @@ hipError_t launch_radius(const F32FwdArgs& a, hipStream_t s) {
     const int fast_ok = ((uintptr_t)a.in % 16 == 0) && (a.pitch % 4 == 0);
     if (!a.smag) {  // absolute thresholds, no max: classify in the walk
         StageTimer t(CANNY_STAGE_F32_WALK, s);
-        launch_walk_sized<R, false>(a, fast_ok, s);
+        if (a.sector)
+            launch_walk_sized<R, false, true>(a, fast_ok, s);
+        else
+            launch_walk_sized<R, false, false>(a, fast_ok, s);
         return hipGetLastError();
     }
     {

@@ -119,6 +119,7 @@ struct F32FwdArgs {
     float* mag;       // optional
     float* max_out;   // optional
     int skip_classify;  // signed path only: the hysteresis pass classifies instead
+    int sector;         // one-launch path only: four-sector direction instead of interpolation
 };
 // stage timing (canny_timing.hip): timing_begin returns a slot (or -1 when
 // timing is off or the stage's pool is full) that timing_end closes

@@ -28,7 +28,7 @@ def lib():
 
 def test_header_declares_the_boundary():
     names = declared_functions()
-    for required in ("canny_u8", "canny_f32", "canny_batch", "canny_mag_backward",
+    for required in ("canny_u8", "canny_f32", "canny_f32_sector", "canny_batch", "canny_mag_backward",
                      "canny_mag_forward", "canny_hysteresis", "canny_batch_plan_create"):
         assert required in names
 
@@ -47,7 +47,7 @@ def test_status_strings_and_pitch(lib):
     assert lib.canny_status_string(0) == b"ok"
     assert lib.canny_status_string(2).startswith(b"workspace")
     assert lib.canny_status_string(99) == b"unknown status"
-    assert lib.canny_abi_version() == 3
+    assert lib.canny_abi_version() == 4
     for W, p in [(0, 0), (1, 4), (4, 4), (5, 4), (16, 4), (17, 8), (4096, 1024), (4097, 1028)]:
         assert lib.canny_class_pitch(W) == p, W
 
@@ -84,6 +84,16 @@ def test_host_validation_f32(lib):
     assert f(FAKE, 8, 8, 8, 1.4, 3, 0.3, 0.2, 1, None, 8, None, None, None, FAKE, n, None) == 1
     assert f(FAKE, 8, 8, 8, float("nan"), 3, 0.1, 0.2, 1, None, 8, None, None, None, FAKE, n, None) == 1
     assert f(FAKE, 8, 8, 8, 1.4, 3, 0.1, 0.2, 1, None, 8, None, None, None, None, n, None) == 2
+
+
+def test_host_validation_f32_sector(lib):
+    n = 1 << 40
+    f = lib.canny_f32_sector
+    assert f(FAKE, 8, 8, 8, 0.0, 3, 10.0, 20.0, None, 8, None, None, FAKE, n, None) == 1
+    assert f(FAKE, 8, 8, 8, 1.4, 0, 10.0, 20.0, None, 8, None, None, FAKE, n, None) == 1
+    assert f(FAKE, 8, 8, 8, 1.4, 3, 30.0, 20.0, None, 8, None, None, FAKE, n, None) == 1
+    assert f(FAKE, 4, 8, 8, 1.4, 3, 10.0, 20.0, None, 8, None, None, FAKE, n, None) == 1
+    assert f(FAKE, 8, 8, 8, 1.4, 3, 10.0, 20.0, None, 8, None, None, None, n, None) == 2
 
 
 def test_host_validation_mag_and_batch(lib):

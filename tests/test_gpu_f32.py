@@ -239,3 +239,99 @@ def test_float_edges_only_absolute_with_max(canny):
     c = unpack_classes(cls.cpu().numpy(), *X.shape)
     assert ((c != oc) & ((amb & 3) == 0)).sum() == 0
     assert abs(float(mx.cpu()[0]) - omx) <= TOL * omx
+
+
+# ---- four-sector variant (absolute thresholds, one launch) -------------------
+
+def check_sector(canny, X, sigma=1.4, R=3, low=None, high=None, tol=TOL):
+    """Classes equal the four-sector oracle's on every pixel it does not flag
+    (threshold, suppression near-tie, sector boundary); strength within the
+    float tolerance; edges = breadth-first search on the GPU's classes."""
+    H, W = X.shape
+    if low is None:
+        lo, hi = absolute_like_relative(X, sigma, R)
+    else:
+        lo, hi = low, high
+    dev = torch.from_numpy(np.ascontiguousarray(X, dtype=np.float32)).cuda()
+    e, cls, mag = canny.canny_f32_sector(dev, sigma, R, lo, hi, return_classes=True,
+                                         return_magnitude=True)
+    torch.cuda.synchronize()
+    c = unpack_classes(cls.cpu().numpy(), H, W)
+    oc, oM, amb, omx = oracle.classify_f32_sector(X, sigma, R, lo, hi, False, tol)
+    err = np.abs(mag.cpu().numpy() - oM) / np.maximum(np.maximum(oM, 0.05 * omx), 1e-30)
+    assert err.max() <= tol or omx == 0.0, f"strength error {err.max():.3g}"
+    unamb = (amb & 11) == 0
+    diff = (c != oc) & unamb
+    assert diff.sum() == 0, f"{diff.sum()} class mismatches at {np.argwhere(diff)[:5].tolist()}"
+    be, _ = oracle.hysteresis(c)
+    assert np.array_equal(e.cpu().numpy(), be)
+    return oc, c
+
+
+def test_sector_512(canny):
+    X = workloads.natural_u8(512, 512, seed=0).astype(np.float32)
+    oc, c = check_sector(canny, X)
+    assert (oc == 2).sum() > 100
+    # the four-sector rule is a different suppression: it keeps other pixels
+    ic, _, _, _ = oracle.classify_f32(X, 1.4, 3, *absolute_like_relative(X), False)
+    assert (ic != oc).sum() > 0
+
+
+@pytest.mark.parametrize("H", [1, 2, 5, 13, 33, 40])
+def test_sector_small_sizes(canny, H):
+    for W in [1, 3, 4, 5, 17, 40, 247, 248, 249]:
+        X = workloads.natural_u8(H, W, seed=500 + H * 64 + W).astype(np.float32)
+        check_sector(canny, X)
+
+
+@pytest.mark.parametrize("R", [1, 2, 3, 4, 5, 6, 7, 8])
+def test_sector_radii(canny, R):
+    X = workloads.natural_u8(97, 301, seed=40 + R).astype(np.float32)
+    sigma = 0.5 + 0.4 * R
+    _, _, _, omx = oracle.classify_f32(X, sigma, R)
+    tol = max(TOL, 16 * 2.0 ** -24 * 255 * (2 * R + 1) / (0.05 * omx))
+    check_sector(canny, X, sigma=sigma, R=R, tol=tol)
+
+
+def test_sector_ragged_and_4096(canny):
+    check_sector(canny, workloads.natural_u8(1001, 2049, seed=14).astype(np.float32))
+    check_sector(canny, workloads.natural_u8(4096, 4096, seed=1).astype(np.float32))
+
+
+def test_sector_balanced_split_shapes(canny):
+    for shape in [(22, 245760), (60, 82000), (3000, 4084)]:
+        check_sector(canny, workloads.natural_u8(*shape, seed=7 + shape[0]).astype(np.float32))
+
+
+def test_sector_axis_and_diagonal_steps_match_interpolated(canny):
+    """Where the gradient lies on an axis or the (1, 1) diagonal the two
+    suppression rules coincide (see the oracle pins); the GPU variants must
+    agree with each other there too."""
+    X = np.full((300, 400), 40.0, np.float32)
+    X[:, 150] = 90.0
+    X[:, 151:] = 170.0
+    dev = torch.from_numpy(X).cuda()
+    a = canny.canny_f32(dev, 1.4, 3, 5.0, 20.0, False)
+    b = canny.canny_f32_sector(dev, 1.4, 3, 5.0, 20.0)
+    assert torch.equal(a, b) and int((a > 0).sum()) == 300
+
+
+def test_sector_unaligned_pitch(canny):
+    X = workloads.natural_u8(77, 301, seed=22).astype(np.float32)
+    H, W = X.shape
+    big = torch.zeros((H, W + 3), dtype=torch.float32, device="cuda")
+    big[:, 1:W + 1] = torch.from_numpy(X).cuda()
+    lo, hi = absolute_like_relative(X)
+    e, cls = canny.canny_f32_sector(big[:, 1:W + 1], 1.4, 3, lo, hi, return_classes=True)
+    c = unpack_classes(cls.cpu().numpy(), H, W)
+    oc, _, amb, _ = oracle.classify_f32_sector(X, 1.4, 3, lo, hi, False, TOL)
+    assert ((c != oc) & ((amb & 11) == 0)).sum() == 0
+    be, _ = oracle.hysteresis(c)
+    assert np.array_equal(e.cpu().numpy(), be)
+
+
+def test_sector_constant(canny):
+    dev = torch.full((100, 300), 7.25, dtype=torch.float32, device="cuda")
+    e, cls = canny.canny_f32_sector(dev, 1.4, 3, 0.0, 1.0, return_classes=True)
+    assert not e.any() and not unpack_classes(cls.cpu().numpy(), 100, 300).any()
+
