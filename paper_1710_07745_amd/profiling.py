@@ -29,7 +29,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 WALK_SOURCES = ("paper_1710_07745_amd/csrc/canny_f32_forward.hip",
                 "paper_1710_07745_amd/csrc/canny_f32_common.h",
                 "paper_1710_07745_amd/csrc/canny_internal.h")
-WALK_KERNEL = "k_f32_forward_bal<3, 40, 23, true>"
+WALK_KERNEL = "k_f32_forward_bal<3, 40, 23, true, false>"
 COPY_KERNEL = "copy"  # the device-to-device copy kernel's name contains this
 
 
