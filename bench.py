@@ -225,6 +225,42 @@ def bench_batch(canny, torch, steps, warmup):
             "speedup_vs_loop": round(t_loop / t_graph, 3), "tuned": info}
 
 
+def bench_video(canny, torch, steps, warmup):
+    """Streaming integer Canny on host frames (PCIe-inclusive): pinned 4K and
+    8K uint8 frames pushed through canny_video_* with a 3-slot ring (uploads,
+    detection and downloads overlapped) and with one slot (each frame's
+    upload waits for the previous download), timed on the host from the
+    first push to the final sync."""
+    import workloads
+    out = {}
+    for label, (H, W), n in (("4k", (2160, 3840), max(40, 2 * steps)),
+                             ("8k", (4320, 7680), max(20, steps))):
+        frames = [torch.from_numpy(workloads.natural_u8(H, W, seed=900 + i)).pin_memory()
+                  for i in range(4)]
+        outs = [torch.empty((H, W), dtype=torch.uint8).pin_memory() for _ in range(4)]
+        res = {}
+        for depth in (3, 1):
+            vs = canny.VideoStream(H, W, 40, 100, depth=depth)
+            for i in range(4):
+                vs.push(frames[i], outs[i])
+            vs.sync()
+            t0 = time.perf_counter()
+            for i in range(n):
+                vs.push(frames[i % 4], outs[i % 4])
+            vs.sync()
+            dt = time.perf_counter() - t0
+            vs.close()
+            res[depth] = n / dt
+        out[label] = {"frames": n, "shape": [H, W], "fps": round(res[3], 1),
+                      "mpix_s": round(res[3] * H * W / 1e6, 1),
+                      "fps_serialized": round(res[1], 1),
+                      "overlap_speedup": round(res[3] / res[1], 3)}
+        del frames, outs
+    out["workload"] = ("streaming integer Canny from pinned host frames to host edge maps "
+                       "(PCIe-inclusive), 3-slot ring vs 1 slot")
+    return out
+
+
 def cpu_baseline(seconds=10.0):
     import numpy as np
     import oracle
@@ -351,7 +387,8 @@ def main():
         configs["u8_16384_spiral"] = bench_u8(canny, torch, workloads.spiral_u8(16384, seed=5),
                                               max(3, args.steps // 5), 2,
                                               "integer Canny, 16384x16384 spiral stress image")
-        for name, fn in (("batch_256_uneven", "bench_batch"), ("mag_fwd_bwd_32x1024", "bench_mag")):
+        for name, fn in (("batch_256_uneven", "bench_batch"), ("mag_fwd_bwd_32x1024", "bench_mag"),
+                         ("video_u8", "bench_video")):
             f = globals().get(fn)
             if f is not None:
                 log(name)

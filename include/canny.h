@@ -187,6 +187,39 @@ int canny_batch_plan_info(const canny_batch_plan* plan, int32_t* fwd_rows, int32
 void canny_batch_plan_destroy(canny_batch_plan* plan);
 
 /* ---------------------------------------------------------------------
+ * Streaming integer Canny over a sequence of host frames of one size (the
+ * operator of canny_u8, Steps 1-4, per frame).
+ *
+ * The stream owns `depth` device slots (frame, edge map, workspace) and
+ * three HIP streams (upload, detect, download; default priority).  A push
+ * enqueues, for the next slot in ring order: the host-to-device copy of
+ * the frame, canny_u8 on it after that copy, and the device-to-host copy of
+ * the edge map after the detection; a slot is reused only after its
+ * previous download has completed.  All ordering is by device events, so
+ * with depth >= 3 copies in both directions overlap the detection.
+ *
+ * canny_video_create: H, W >= 1, H*W <= 2^31, 0 <= low <= high,
+ *   1 <= depth <= 16; *out receives a host-owned handle.  Allocates device
+ *   memory and streams (owned by the handle).  Errors: CANNY_ERR_INVALID,
+ *   CANNY_ERR_UNSUPPORTED (device is not gfx950), CANNY_ERR_HIP.
+ * canny_video_push: host_frame (H x W uint8, row pitch W) and host_edges
+ *   (H x W uint8 output, 255 / 0) are HOST pointers; they must stay valid
+ *   and unmodified (frame) / unread (edges) until canny_video_sync returns.
+ *   Copies are asynchronous only for pinned host memory (hipHostMalloc);
+ *   pageable memory works but the runtime may stage it synchronously.
+ *   Returns at once; errors: CANNY_ERR_INVALID on NULL, CANNY_ERR_HIP.
+ * canny_video_sync: waits until every pushed frame's edge map is in host
+ *   memory.
+ * canny_video_destroy: waits, then frees the handle.  Not thread-safe: one
+ *   host thread per handle.
+ */
+typedef struct canny_video canny_video;
+int canny_video_create(int H, int W, int32_t low, int32_t high, int depth, canny_video** out);
+int canny_video_push(canny_video* v, const uint8_t* host_frame, uint8_t* host_edges);
+int canny_video_sync(canny_video* v);
+void canny_video_destroy(canny_video* v);
+
+/* ---------------------------------------------------------------------
  * Differentiable front end M(I, sigma) = |Sobel * G_sigma * I| (Steps 1-2,
  * L2 strength), batched over N images of equal size, one sigma per image.
  *

@@ -20,7 +20,7 @@ from . import _lib
 from ._lib import CannyError, check, lib
 
 __all__ = [
-    "canny_u8", "canny_f32", "canny_f32_sector", "hysteresis", "class_pitch", "u8_workspace_bytes", "f32_workspace_bytes",
+    "canny_u8", "canny_f32", "canny_f32_sector", "VideoStream", "hysteresis", "class_pitch", "u8_workspace_bytes", "f32_workspace_bytes",
     "BatchPlan", "mag_forward", "mag_backward", "CannyMagnitude", "canny_magnitude",
     "CannyError", "StageTiming",
 ]
@@ -161,6 +161,55 @@ def canny_f32_sector(img: torch.Tensor, sigma: float = 1.4, radius: int = 3, low
     if return_magnitude:
         out.append(mag)
     return out[0] if len(out) == 1 else tuple(out)
+
+
+class VideoStream:
+    """Streaming integer Canny over host frames of one size: uploads, detection
+    and downloads of successive frames overlap on three HIP streams, with a
+    ring of ``depth`` device slots.  See canny_video_create.  Frames and edge
+    buffers are CPU uint8 tensors of shape (H, W) (pinned ones copy
+    asynchronously) and must stay untouched until ``sync()``."""
+
+    def __init__(self, H: int, W: int, low: int = 40, high: int = 100, depth: int = 3,
+                 device=None):
+        self.H, self.W = int(H), int(W)
+        self.device = torch.device(device or "cuda")
+        handle = C.c_void_p()
+        with torch.cuda.device(self.device):
+            st = lib().canny_video_create(self.H, self.W, int(low), int(high), int(depth),
+                                          C.byref(handle))
+        check("canny_video_create", st)
+        self._h = handle
+
+    def _host(self, t: torch.Tensor, name: str):
+        if t.device.type != "cpu" or t.dtype != torch.uint8 or tuple(t.shape) != (self.H, self.W) \
+                or not t.is_contiguous():
+            raise ValueError(f"{name}: expected a contiguous CPU uint8 tensor of shape "
+                             f"({self.H}, {self.W})")
+        return t.data_ptr()
+
+    def push(self, frame: torch.Tensor, edges: torch.Tensor) -> None:
+        if not self._h:
+            raise ValueError("video stream is closed")
+        with torch.cuda.device(self.device):
+            st = lib().canny_video_push(self._h, self._host(frame, "frame"),
+                                        self._host(edges, "edges"))
+        check("canny_video_push", st)
+
+    def sync(self) -> None:
+        if self._h:
+            check("canny_video_sync", lib().canny_video_sync(self._h))
+
+    def close(self) -> None:
+        if self._h:
+            lib().canny_video_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class BatchPlan:

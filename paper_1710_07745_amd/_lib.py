@@ -43,6 +43,10 @@ SIGNATURES = {
     "canny_batch": (C.c_int, [P, P, P, P, P, P, sz, P]),
     "canny_batch_plan_info": (C.c_int, [P, P, P]),
     "canny_batch_plan_destroy": (None, [P]),
+    "canny_video_create": (C.c_int, [C.c_int, C.c_int, i32, i32, C.c_int, C.POINTER(P)]),
+    "canny_video_push": (C.c_int, [P, P, P]),
+    "canny_video_sync": (C.c_int, [P]),
+    "canny_video_destroy": (None, [P]),
     "canny_mag_forward": (C.c_int, [P, P, C.c_int, C.c_int, C.c_int, C.c_int, P, P]),
     "canny_mag_backward_workspace_bytes": (sz, [C.c_int, C.c_int, C.c_int, C.c_int]),
     "canny_mag_backward": (C.c_int, [P, P, P, C.c_int, C.c_int, C.c_int, C.c_int, P, P, P, sz, P]),

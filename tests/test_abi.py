@@ -96,6 +96,18 @@ def test_host_validation_f32_sector(lib):
     assert f(FAKE, 8, 8, 8, 1.4, 3, 10.0, 20.0, None, 8, None, None, None, n, None) == 2
 
 
+def test_host_validation_video(lib):
+    out = C.c_void_p()
+    assert lib.canny_video_create(0, 8, 1, 2, 3, C.byref(out)) == 1
+    assert lib.canny_video_create(8, 8, 3, 2, 3, C.byref(out)) == 1
+    assert lib.canny_video_create(8, 8, 1, 2, 0, C.byref(out)) == 1
+    assert lib.canny_video_create(8, 8, 1, 2, 17, C.byref(out)) == 1
+    assert lib.canny_video_create(8, 8, 1, 2, 3, None) == 1
+    assert lib.canny_video_push(None, FAKE, FAKE) == 1
+    assert lib.canny_video_sync(None) == 1
+    lib.canny_video_destroy(None)
+
+
 def test_host_validation_mag_and_batch(lib):
     assert lib.canny_mag_forward(None, FAKE, 1, 8, 8, 9, FAKE, None) == 1
     assert lib.canny_mag_forward(FAKE, FAKE, 1, 8, 8, 13, C.c_void_p(0x900000), None) == 1
