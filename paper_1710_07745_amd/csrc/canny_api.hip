@@ -110,7 +110,7 @@ int canny_u8(const uint8_t* in, int64_t in_pitch, int H, int W, int32_t low, int
     hipError_t e;
     {
         StageTimer t(CANNY_STAGE_U8_FORWARD, s);
-        e = launch_u8_forward(f, 32, s);
+        e = launch_u8_forward(f, 0, s);  // balanced block heights
     }
     if (e != hipSuccess || !edges) return status_of(e);
     HystArgs h;

@@ -71,6 +71,20 @@ def test_unaligned_pitch(canny, pad, offset):
     check_exact(canny, workloads.natural_u8(123, 301, seed=5), pitch_pad=pad, offset=offset)
 
 
+# Shapes for the balanced forward launch (interior blocks of 40 rows, border
+# blocks of 20): images under 20 rows, exactly 40 rows (no interior block),
+# 55 rows (two bottom border blocks), three border strips (the right halo of
+# the second-to-last strip leaves the image), and every strip bordered (rows
+# not 4-byte aligned).
+@pytest.mark.parametrize("H,W", [(19, 253952), (40, 130000), (55, 90000), (3000, 4218)])
+def test_balanced_split_shapes(canny, H, W):
+    check_exact(canny, workloads.natural_u8(H, W, seed=H + W))
+
+
+def test_balanced_split_unaligned(canny):
+    check_exact(canny, workloads.natural_u8(2048, 4096, seed=44), pitch_pad=3, offset=1)
+
+
 def test_step_edge_golden(canny):
     for D, expect_line in [(15, False), (16, False), (40, False), (41, False), (42, True), (120, True)]:
         for transpose in (False, True):
