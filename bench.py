@@ -7,8 +7,10 @@ of the largest strength, 8-connected hysteresis -- on a 4096x4096 fp32 image,
 in MPix/s.  One step = one full pass of the operator over one image.  Inputs
 are seeded synthetic images (value-noise shading + 40 step-edged shapes +
 noise, see workloads.py) already resident in HBM; the step rotates through
-enough distinct input/output buffers (> 256 MB) that the 256 MB Infinity Cache
-cannot hold them, so every step streams from HBM.
+enough distinct input/output buffers (>= 1 GiB, 4x the 256 MB Infinity Cache)
+that no step finds its input there, so every step streams from HBM.  The
+line also gives per-step percentiles of the same steps and, labelled as such,
+the rate with one buffer set reused (cache-warm).
 
 Also reported (under "configs"): the integer pipeline at 4096^2 and on the
 16384^2 hysteresis stress image, the float pipeline at 7680x4320, the batched
@@ -55,7 +57,24 @@ def timed(fn, steps, warmup, stream):
 
 
 def n_rot(bytes_per_set):
-    return max(2, -(-2 * MALL_BYTES // max(bytes_per_set, 1)))
+    """Distinct buffer sets to rotate through: >= 1 GiB in total, 4x the
+    Infinity Cache, so that no step finds its input there."""
+    return max(2, -(-4 * MALL_BYTES // max(bytes_per_set, 1)))
+
+
+def step_percentiles(fn, steps, stream):
+    """p10 / p50 / p90 of single-step device times (one event pair per step)."""
+    import torch
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    for a, b in evs:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    t = sorted(a.elapsed_time(b) for a, b in evs)
+    pick = lambda q: round(t[min(len(t) - 1, int(q * len(t)))], 4)
+    return {"p10": pick(0.1), "p50": pick(0.5), "p90": pick(0.9)}
 
 
 def bench_f32(canny, torch, H, W, steps, warmup, seed, sector=False):
@@ -78,6 +97,13 @@ def bench_f32(canny, torch, H, W, steps, warmup, seed, sector=False):
 
     st = torch.cuda.current_stream()
     ms = timed(step, steps, warmup, st)
+    if not sector and (H, W) == (4096, 4096):
+        pct = step_percentiles(step, steps, st)  # rotating buffers, per step
+        warm = timed(lambda: canny.canny_f32(xs[0], 1.4, 3, 0.05, 0.15, True, edges=es[0],
+                                             workspace=ws), steps, warmup, st)
+        return ({"ms": ms, "mpix_s": H * W / (ms * 1e-3) / 1e6, "rot_buffers": k,
+                 "step_ms_percentiles": pct,
+                 "warm_same_buffer_mpix_s": round(H * W / (warm * 1e-3) / 1e6, 1)}, (xs, es, ws))
     return {"ms": ms, "mpix_s": H * W / (ms * 1e-3) / 1e6, "rot_buffers": k}, (xs, es, ws)
 
 
@@ -415,6 +441,8 @@ def main():
         "config": {"workload": "float Canny (sigma 1.4, 7 taps, L2, interpolated NMS, relative "
                                "thresholds 0.05/0.15, hysteresis), one 4096x4096 fp32 image per step",
                    "image": [4096, 4096], "rotating_buffers": head["rot_buffers"]},
+        "step_ms_percentiles": head.get("step_ms_percentiles"),
+        "warm_same_buffer_mpix_s": head.get("warm_same_buffer_mpix_s"),
         "roofline": roof,
         "cpu_baseline": cpu,
         "cpu_paper_design": cpu_pd,
