@@ -13,7 +13,6 @@
 // pinned).  Every stream is created at the default priority.
 #include <hip/hip_runtime.h>
 
-#include <cstring>
 #include <vector>
 
 #include "../../include/canny.h"
