@@ -6,6 +6,8 @@
   python -m paper_1710_07745_amd.profiling valu PMC_DIR [--kernel SUBSTR] [--command C ...]
       VALU instructions (SQ_INSTS_VALU, per wave) and waves (SQ_WAVES) per
       launch of the kernel, from one counter run (median over dispatches).
+  python -m paper_1710_07745_amd.profiling counters PMC_DIR --kernel SUBSTR [--kernel ...]
+      every counter of one run, median per dispatch, for each kernel named.
   python -m paper_1710_07745_amd.profiling traffic FETCH_DIR WRITE_DIR
       --kernel SUBSTR --copy-bytes N [--command C ...]
       HBM bytes per launch of the kernel whose name contains SUBSTR, from two
@@ -147,6 +149,22 @@ def valu(args) -> None:
     print(f"valu_insts_per_wave: {insts / max(waves, 1):.1f}")
 
 
+def counters(args) -> None:
+    rows = list(csv.DictReader(open(_one(os.path.join(args.dir, "*counter_collection.csv")))))
+    names = sorted({r["Counter_Name"] for r in rows})
+    print("# hardware counters per dispatch (median over dispatches)")
+    for c in args.command or []:
+        print(f"# command: {c}")
+    print(f"{'kernel':44s} " + " ".join(f"{n:>20s}" for n in names))
+    for k in args.kernel:
+        vals = []
+        for n in names:
+            v = sorted(float(r["Counter_Value"]) for r in rows
+                       if r["Counter_Name"] == n and k in r["Kernel_Name"])
+            vals.append(f"{v[len(v) // 2]:20.0f}" if v else f"{'-':>20s}")
+        print(f"{k[:44]:44s} " + " ".join(vals))
+
+
 def main(argv=None) -> None:
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -165,8 +183,12 @@ def main(argv=None) -> None:
     v.add_argument("dir")
     v.add_argument("--kernel", default=WALK_KERNEL)
     v.add_argument("--command", action="append")
+    c = sub.add_parser("counters")
+    c.add_argument("dir")
+    c.add_argument("--kernel", action="append", required=True)
+    c.add_argument("--command", action="append")
     a = ap.parse_args(argv)
-    {"stats": stats, "traffic": traffic, "valu": valu}[a.cmd](a)
+    {"stats": stats, "traffic": traffic, "valu": valu, "counters": counters}[a.cmd](a)
 
 
 if __name__ == "__main__":

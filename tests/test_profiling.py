@@ -69,3 +69,14 @@ def test_valu_summary(tmp_path, capsys):
     assert profiling.read_valu(str(p)) == 8500.0
     p.write_text("source_sha256: 0\nvalu_insts_per_launch: 8500\n")
     assert profiling.read_valu(str(p)) is None
+
+
+def test_counters_table(tmp_path, capsys):
+    d = str(tmp_path / "c")
+    write_counters(d, [["k_a(x)", "SQ_WAVES", 4.0], ["k_a(x)", "SQ_WAVES", 6.0], ["k_a(x)", "SQ_WAVES", 5.0],
+                       ["k_a(x)", "SQ_WAIT_ANY", 9.0], ["k_b(y)", "SQ_WAVES", 1.0]])
+    profiling.main(["counters", d, "--kernel", "k_a", "--kernel", "k_b"])
+    lines = [ln.split() for ln in capsys.readouterr().out.splitlines() if not ln.startswith("#")]
+    assert lines[0] == ["kernel", "SQ_WAIT_ANY", "SQ_WAVES"]
+    assert lines[1] == ["k_a", "9", "5"]
+    assert lines[2] == ["k_b", "-", "1"]
