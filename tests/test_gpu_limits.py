@@ -1,0 +1,55 @@
+"""The largest sizes the boundary accepts, per axis (H, W <= 2^20; the C ABI
+rejects more): parity with the oracle on a 3 x 2^20 and a 2^20 x 3 image for
+the integer, float and four-sector paths, and rejection one past the limit."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from helpers import unpack_classes
+
+pytestmark = pytest.mark.gpu
+MAXD = 1 << 20
+
+
+@pytest.fixture(scope="module")
+def canny():
+    import paper_1710_07745_amd as m
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return m
+
+
+@pytest.mark.parametrize("shape", [(3, MAXD), (MAXD, 3)])
+def test_max_extent_u8(canny, shape):
+    img = workloads.natural_u8(*shape, seed=77)
+    e, cls = canny.canny_u8(torch.from_numpy(img).cuda(), 40, 100, return_classes=True)
+    oe, oc = oracle.canny_u8(img, 40, 100)
+    assert np.array_equal(unpack_classes(cls.cpu().numpy(), *shape), oc)
+    assert np.array_equal(e.cpu().numpy(), oe)
+
+
+@pytest.mark.parametrize("shape", [(3, MAXD), (MAXD, 3)])
+def test_max_extent_f32(canny, shape):
+    X = workloads.natural_u8(*shape, seed=78).astype(np.float32)
+    dev = torch.from_numpy(X).cuda()
+    e, cls = canny.canny_f32(dev, return_classes=True)
+    oc, _, amb, _ = oracle.classify_f32(X)
+    c = unpack_classes(cls.cpu().numpy(), *shape)
+    assert ((c != oc) & ((amb & 3) == 0)).sum() == 0
+    assert np.array_equal(e.cpu().numpy(), oracle.hysteresis(c)[0])
+    _, _, _, mx = oracle.classify_f32(X)
+    e2, cls2 = canny.canny_f32_sector(dev, 1.4, 3, 0.05 * mx, 0.15 * mx, return_classes=True)
+    oc2, _, amb2, _ = oracle.classify_f32_sector(X, 1.4, 3, 0.05 * mx, 0.15 * mx)
+    c2 = unpack_classes(cls2.cpu().numpy(), *shape)
+    assert ((c2 != oc2) & ((amb2 & 11) == 0)).sum() == 0
+    assert np.array_equal(e2.cpu().numpy(), oracle.hysteresis(c2)[0])
+
+
+def test_one_past_the_limit_is_rejected(canny):
+    x = torch.zeros((2, MAXD + 1), dtype=torch.uint8, device="cuda")
+    with pytest.raises(canny.CannyError):
+        canny.canny_u8(x)
+    y = torch.zeros((2, MAXD + 1), dtype=torch.float32, device="cuda")
+    with pytest.raises(canny.CannyError):
+        canny.canny_f32(y)
