@@ -531,6 +531,17 @@ WalkPlan make_walk_plan(int H, int W, int fast_ok) {
     return p;
 }
 
+// The interior conditions the balanced kernel relies on, checked on the host
+// (they hold by construction): every interior block and every interior strip
+// has its halo inside the image, and interior waves read 16-byte aligned rows.
+template <int R>
+bool walk_plan_ok(const WalkPlan& p, int H, int W, int fast_ok) {
+    constexpr int SC = WalkShape<R>::SC, HL = WalkShape<R>::HL, HR = WalkShape<R>::HR;
+    if (p.n_is == 0 || p.k == 0) return true;  // no interior block
+    return fast_ok && kRRE - HR >= 0 && kRRE + p.k * kRRI + HR <= H && SC - 4 * HL >= 0 &&
+           (int64_t)p.sr * SC + 4 * HL <= W;  // last interior strip is sr - 1
+}
+
 // Rows per wave: a wave walks its strip serially, so long strips suit large
 // images (halo rows amortised) and short ones small images (more waves in
 // flight).  The balanced split unless that leaves fewer than 1024 waves (one
@@ -538,7 +549,7 @@ WalkPlan make_walk_plan(int H, int W, int fast_ok) {
 template <int R, bool SIGNED, bool SECTOR = false>
 void launch_walk_sized(const F32FwdArgs& a, int fast_ok, hipStream_t s) {
     const WalkPlan p = make_walk_plan<R>(a.H, a.W, fast_ok);
-    if (p.nwaves >= 1024) {
+    if (p.nwaves >= 1024 && walk_plan_ok<R>(p, a.H, a.W, fast_ok)) {
         hipLaunchKernelGGL((k_f32_forward_bal<R, kRRI, kRRE, SIGNED, SECTOR>), dim3(ceil_div(p.nwaves, kWavesPerWG)),
                            dim3(kWGThreads), 0, s, a, p, fast_ok);
     } else {

@@ -471,6 +471,15 @@ static U8Plan make_u8_plan(int H, int W, int fast_ok) {
     return p;
 }
 
+// The interior conditions the balanced kernel relies on, checked on the host
+// (they hold by construction): halo rows and columns of every interior block
+// inside the image, 4-byte aligned rows.
+static bool u8_plan_ok(const U8Plan& p, int H, int W, int fast_ok) {
+    if (p.n_is == 0 || p.k == 0) return true;  // no interior block
+    return fast_ok && kU8RRE >= 4 && kU8RRE + p.k * kU8RRI + 4 <= H &&
+           (int64_t)p.sr * kU8StripCols + 4 <= W;  // last interior strip is sr - 1
+}
+
 // rows_per_wave <= 0: the balanced split (32-row blocks everywhere when it
 // would give fewer than 1024 waves, one per SIMD); otherwise that block
 // height for every strip.
@@ -478,7 +487,7 @@ hipError_t launch_u8_forward(const U8FwdArgs& a, int rows_per_wave, hipStream_t 
     if (rows_per_wave <= 0) {
         const int fast_ok = ((uintptr_t)a.in % 4 == 0) && (a.pitch % 4 == 0);
         const U8Plan p = make_u8_plan(a.H, a.W, fast_ok);
-        if (p.nwaves < 1024) return launch_r<32>(a, s);
+        if (p.nwaves < 1024 || !u8_plan_ok(p, a.H, a.W, fast_ok)) return launch_r<32>(a, s);
         hipLaunchKernelGGL((k_u8_forward_bal<kU8RRI, kU8RRE>), dim3(ceil_div(p.nwaves, kWavesPerWG)),
                            dim3(kWGThreads), 0, s, a, p, fast_ok);
         return hipGetLastError();
