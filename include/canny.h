@@ -198,7 +198,8 @@ void canny_batch_plan_destroy(canny_batch_plan* plan);
  * previous download has completed.  All ordering is by device events, so
  * with depth >= 3 copies in both directions overlap the detection.
  *
- * canny_video_create: H, W >= 1, H*W <= 2^31, 0 <= low <= high,
+ * canny_video_create: H, W as canny_u8 accepts them (1 <= H, W <= 2^20 and
+ *   ceil(H/64) * ceil(W/64) * 4096 < 2^31), 0 <= low <= high,
  *   1 <= depth <= 16; *out receives a host-owned handle.  Allocates device
  *   memory and streams (owned by the handle).  Errors: CANNY_ERR_INVALID,
  *   CANNY_ERR_UNSUPPORTED (device is not gfx950), CANNY_ERR_HIP.

@@ -32,8 +32,16 @@ EXTRA = {
 EXTRA.update({f"canny_mag_g{g}.hip": UNROLL + ["-fno-honor-nans"] for g in range(1, 7)})
 
 
-def _compile(src: str) -> str:
+def _headers_mtime() -> float:
+    hdrs = glob.glob(os.path.join(CSRC, "*.h")) + glob.glob(os.path.join(HERE, "..", "include", "*.h"))
+    return max((os.path.getmtime(h) for h in hdrs), default=0.0)
+
+
+def _compile(src: str, incremental: bool = False) -> str:
     obj = os.path.join(OBJ, os.path.basename(src) + ".o")
+    if incremental and os.path.exists(obj) and \
+            os.path.getmtime(obj) > max(os.path.getmtime(src), _headers_mtime()):
+        return obj
     cmd = [HIPCC] + FLAGS + EXTRA.get(os.path.basename(src), []) + ["-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -41,14 +49,16 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(jobs: int | None = None) -> str:
+def build(jobs: int | None = None, incremental: bool = False) -> str:
+    """Compile every HIP source (incremental: only those older than their
+    object file or any header) and link libcanny.so."""
     os.makedirs(OBJ, exist_ok=True)
     # the long (unrolled) compiles first, so they overlap the short ones
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")),
                   key=lambda f: (os.path.basename(f) not in EXTRA, f))
     jobs = jobs or min(8, os.cpu_count() or 4, len(srcs))
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
+        objs = list(ex.map(lambda f: _compile(f, incremental), srcs))
     tmp = LIB + ".tmp"
     subprocess.check_call([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs)
     os.replace(tmp, LIB)
@@ -56,4 +66,5 @@ def build(jobs: int | None = None) -> str:
 
 
 if __name__ == "__main__":
-    print(build(int(sys.argv[1]) if len(sys.argv) > 1 else None))
+    args = [a for a in sys.argv[1:] if a != "--incremental"]
+    print(build(int(args[0]) if args else None, incremental="--incremental" in sys.argv))

@@ -19,6 +19,7 @@
 
 namespace canny {
 bool device_ok();
+bool size_ok(int H, int W);
 }  // namespace canny
 
 struct canny_video {
@@ -62,8 +63,9 @@ void release(canny_video* v) {
 extern "C" {
 
 int canny_video_create(int H, int W, int32_t low, int32_t high, int depth, canny_video** out) {
-    if (!out || H < 1 || W < 1 || (int64_t)H * W > ((int64_t)1 << 31) || low < 0 || low > high ||
-        depth < 1 || depth > kMaxDepth)
+    // the frame sizes canny_u8 accepts (each side <= 2^20, and the hysteresis
+    // tile bound), checked here so that no push can fail on the size
+    if (!out || !canny::size_ok(H, W) || low < 0 || low > high || depth < 1 || depth > kMaxDepth)
         return CANNY_ERR_INVALID;
     *out = nullptr;
     if (!canny::device_ok()) return CANNY_ERR_UNSUPPORTED;

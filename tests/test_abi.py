@@ -103,6 +103,9 @@ def test_host_validation_video(lib):
     assert lib.canny_video_create(8, 8, 1, 2, 0, C.byref(out)) == 1
     assert lib.canny_video_create(8, 8, 1, 2, 17, C.byref(out)) == 1
     assert lib.canny_video_create(8, 8, 1, 2, 3, None) == 1
+    # sizes canny_u8 rejects are rejected at creation: a side above 2^20
+    assert lib.canny_video_create(1, (1 << 20) + 1, 1, 2, 3, C.byref(out)) == 1
+    assert lib.canny_video_create((1 << 20) + 1, 1, 1, 2, 3, C.byref(out)) == 1
     assert lib.canny_video_push(None, FAKE, FAKE) == 1
     assert lib.canny_video_sync(None) == 1
     lib.canny_video_destroy(None)

@@ -41,17 +41,26 @@ def run_f32(canny, X, with_max=True, **kw):
 
 
 def check_float(canny, X, sigma=1.4, R=3, low=0.05, high=0.15, relative=True, max_unamb_diff=0,
-                tol=TOL, with_max=True):
+                tol=TOL, with_max=True, excuse_tol=None, label=""):
+    """Strength within ``tol`` (relative, floored at 0.05 max M); classes equal
+    the oracle's wherever it flags no decision within ``excuse_tol`` (default
+    ``tol``) of a threshold or a suppression tie; edges equal BFS on the GPU's
+    classes.  Prints the achieved strength error and the number of excused
+    pixels that differ."""
+    excuse_tol = tol if excuse_tol is None else excuse_tol
     e, c, m, mx = run_f32(canny, X, with_max=with_max, sigma=sigma, radius=R, low=low, high=high,
                           relative=relative)
-    oc, oM, amb, omx = oracle.classify_f32(X, sigma, R, low, high, relative, tol)
+    oc, oM, amb, omx = oracle.classify_f32(X, sigma, R, low, high, relative, excuse_tol)
     floor = 0.05 * omx
     err = np.abs(m - oM) / np.maximum(np.maximum(oM, floor), 1e-30)
+    unamb = (amb & 3) == 0
+    diff = (c != oc) & unamb
+    print(f"[float {label} {X.shape[0]}x{X.shape[1]} R={R}] strength error {err.max():.3g} "
+          f"(bound {tol:.3g}); excused pixels {int((~unamb).sum())}, of which differ "
+          f"{int(((c != oc) & ~unamb).sum())}", flush=True)
     assert err.max() <= tol or omx == 0.0, f"strength error {err.max():.3g}"
     if with_max:
         assert abs(mx - omx) <= tol * omx
-    unamb = (amb & 3) == 0
-    diff = (c != oc) & unamb
     assert diff.sum() <= max_unamb_diff, f"{diff.sum()} class mismatches at {np.argwhere(diff)[:5].tolist()}"
     be, _ = oracle.hysteresis(c)
     assert np.array_equal(e, be)
@@ -134,6 +143,29 @@ def test_float_unaligned_pitch(canny):
         assert np.array_equal(e.cpu().numpy(), be)
 
 
+@pytest.mark.parametrize("kind", ["dc_offset", "low_contrast_dc", "hdr", "tiny", "mixed_range", "ramp"])
+def test_float_value_ranges(canny, kind):
+    """The strength bound on content away from 0..255: a DC offset of 1000,
+    low contrast on that offset (values 1000..1002.55), a high dynamic range
+    (x1000), tiny values (x1e-3), a left half at 1 % contrast beside a
+    full-contrast right half, and the scene on a ramp rising by 5000 across
+    the image."""
+    X = workloads.natural_u8(512, 768, seed=5).astype(np.float32)
+    if kind == "dc_offset":
+        X = X + np.float32(1000.0)
+    elif kind == "low_contrast_dc":
+        X = X * np.float32(0.01) + np.float32(1000.0)
+    elif kind == "hdr":
+        X = X * np.float32(1000.0)
+    elif kind == "tiny":
+        X = X * np.float32(1e-3)
+    elif kind == "mixed_range":
+        X[:, :384] *= np.float32(0.01)
+    else:
+        X = X + np.linspace(0.0, 5000.0, X.shape[1], dtype=np.float32)[None, :]
+    check_float(canny, X, label=kind)
+
+
 def test_float_constant(canny):
     e, c, m, mx = run_f32(canny, np.full((100, 300), 7.25, np.float32))
     assert not e.any() and not c.any() and not m.any() and mx == 0.0
@@ -204,25 +236,39 @@ def test_float_stage_timing(canny):
     assert torch.equal(e, ref_e) and torch.equal(c[:, :nb], ref_c[:, :nb])
 
 
-@pytest.mark.parametrize("shape", [(1, 1), (5, 7), (63, 65), (200, 333), (1001, 2049), (4096, 4096),
-                                   (4320, 7680)])
-def test_float_edges_only_path(canny, shape):
+@pytest.mark.parametrize("shape,seed", [((1, 1), 78), ((5, 7), 82), ((63, 65), 140), ((200, 333), 277),
+                                        ((1001, 2049), 1078), ((4096, 4096), 1), ((4320, 7680), 2)])
+def test_float_edges_only_path(canny, shape, seed):
     """Edges alone (no class map or strength requested) take the path where
-    the hysteresis pass classifies from the signed strength map; it must give
-    the same edges, bit for bit, as the path through an explicit class map,
-    and those equal BFS on that class map."""
+    the hysteresis pass classifies from the signed strength map.  Its edges
+    must equal, bit for bit, those of the path through an explicit class map
+    and BFS on that class map; that class map must equal the oracle's on
+    every pixel the oracle does not flag.  Seeds 1 (4096^2) and 2
+    (7680x4320) are the benchmark's own images.  The number of final edge
+    pixels that differ from the pure oracle (its classes, its BFS) is
+    printed; they can differ only through components joined or split at
+    flagged pixels, and are bounded here at 1e-4 of the image."""
     H, W = shape
-    X = workloads.natural_u8(H, W, seed=77 + H).astype(np.float32)
+    X = workloads.natural_u8(H, W, seed=seed).astype(np.float32)
     dev = torch.from_numpy(X).cuda()
     e_fused, mx = canny.canny_f32(dev, return_max=True)
     e_cls, cls = canny.canny_f32(dev, return_classes=True)
     torch.cuda.synchronize()
     assert torch.equal(e_fused, e_cls)
-    be, _ = oracle.hysteresis(unpack_classes(cls.cpu().numpy(), H, W))
-    assert np.array_equal(e_fused.cpu().numpy(), be)
-    if H * W <= 1 << 20:
-        _, _, _, omx = oracle.classify_f32(X, 1.4, 3)
-        assert abs(float(mx.cpu()[0]) - omx) <= TOL * omx
+    c = unpack_classes(cls.cpu().numpy(), H, W)
+    e = e_fused.cpu().numpy()
+    be, _ = oracle.hysteresis(c)
+    assert np.array_equal(e, be)
+    oc, _, amb, omx = oracle.classify_f32(X, 1.4, 3, 0.05, 0.15, True, TOL)
+    assert abs(float(mx.cpu()[0]) - omx) <= TOL * omx
+    unamb = (amb & 3) == 0
+    assert ((c != oc) & unamb).sum() == 0
+    oe, _ = oracle.hysteresis(oc)
+    ndiff = int((e != oe).sum())
+    print(f"[edges-only {H}x{W} seed {seed}] class differences at flagged pixels "
+          f"{int(((c != oc) & ~unamb).sum())} of {int((~unamb).sum())}; final edge pixels "
+          f"differing from the pure oracle {ndiff} of {int((oe > 0).sum())} edge pixels", flush=True)
+    assert ndiff <= max(1, 1e-4 * H * W)
 
 
 def test_float_edges_only_absolute_with_max(canny):

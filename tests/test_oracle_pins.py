@@ -493,3 +493,179 @@ def test_mag_constant_image_zero_gradient():
     I = np.full((20, 20), 0.4)
     dI, ds = oracle.mag_backward(I, 2.0, np.ones((20, 20)), 9)
     assert not dI.any() and ds == 0.0
+
+
+# ------------------------------------------ float ambiguity flags (bits 0, 1, 3)
+#
+# The flags decide which float-path class differences the GPU parity tests
+# forgive (a decision within tol of flipping), so each bit is pinned here by a
+# case whose strength profile is known in closed form, with the tolerance
+# placed once inside (flag set) and once outside (flag clear) the band.
+
+def _library_taps(sigma, R):
+    """Normalised sampled Gaussian taps g_0..g_R from scipy's impulse response."""
+    imp = np.zeros(4 * R + 1)
+    imp[2 * R] = 1.0
+    g = ndi.gaussian_filter1d(imp, sigma, mode="constant", radius=R)[R:3 * R + 1]
+    return g[R:]  # g_0 .. g_R
+
+
+def _step_image(a, b, c=20, H=16, W=40, mid=None):
+    """Vertical step a | b at column c (optionally one column of value mid at c)."""
+    X = np.full((H, W), a, np.float32)
+    X[:, c:] = b
+    if mid is not None:
+        X[:, c] = mid
+    return X
+
+
+def _step_profile(delta, g):
+    """Closed-form strength of a vertical step of contrast delta (sigma 1.4, R 3)
+    by column offset from the step: rows are constant, so Gy = 0 and
+    Gx(x) = 4 (B(x+1) - B(x-1)); with B(x) = a + delta * sum_{k >= c-x} g_k this
+    is 4 delta (g_{c-x-1} + g_{c-x}).  Keys are x - c."""
+    gg = lambda k: g[abs(k)] if abs(k) < len(g) else 0.0
+    return {d: 4.0 * delta * (gg(-d - 1) + gg(-d)) for d in range(-6, 6)}
+
+
+TOL_PIN = 1e-5
+
+
+def test_step_profile_closed_form():
+    g = _library_taps(1.4, 3)
+    X = _step_image(60.0, 160.0)
+    _, M, _, mx = oracle.classify_f32(X, 1.4, 3, 1.0, 2.0, False)
+    prof = _step_profile(100.0, g)
+    for d, m in prof.items():
+        assert np.allclose(M[:, 20 + d], m, rtol=1e-12, atol=1e-10), d
+    assert mx == pytest.approx(prof[-1], rel=1e-12)
+
+
+@pytest.mark.parametrize("which", ["low", "high"])
+@pytest.mark.parametrize("variant", ["interpolated", "sector"])
+def test_flag_threshold_band(which, variant):
+    """Bit 0: |M - t| <= tol * t for a threshold t.  Thresholds placed at
+    M (1 -+ tol/2) of a column whose M is known set the flag there; at
+    M (1 -+ 3 tol) they leave it clear.  The column three pixels before the
+    step has M = 0.26 * max M, so a band measured in units of the largest
+    strength (or of M instead of t by more than rounding) would not pass."""
+    g = _library_taps(1.4, 3)
+    X = _step_image(60.0, 160.0)
+    prof = _step_profile(100.0, g)
+    fn = oracle.classify_f32 if variant == "interpolated" else oracle.classify_f32_sector
+    for d in (-1, -3):  # the peak (a kept pixel) and a flank pixel
+        m = prof[d]
+        for f, expect in ((1 + TOL_PIN / 2, True), (1 - TOL_PIN / 2, True),
+                          (1 + 3 * TOL_PIN, False), (1 - 3 * TOL_PIN, False)):
+            t = m * f
+            lo, hi = (t, 10 * prof[-1]) if which == "low" else (1e-3, t)
+            cls, M, amb, _ = fn(X, 1.4, 3, lo, hi, False, TOL_PIN)
+            assert np.all(((amb[:, 20 + d] & 1) != 0) == expect), (d, f)
+            # far from every threshold elsewhere: no other column carries bit 0
+            others = [20 + k for k in prof if k != d and abs(prof[k] - t) > 0.01 * t]
+            assert not (amb[:, others] & 1).any()
+        if d == -1 and which == "high":
+            # at the peak the band is where the class flips between weak and strong
+            c_in = fn(X, 1.4, 3, 1e-3, m * (1 - 3 * TOL_PIN), False, TOL_PIN)[0][:, 19]
+            c_out = fn(X, 1.4, 3, 1e-3, m * (1 + 3 * TOL_PIN), False, TOL_PIN)[0][:, 19]
+            assert np.all(c_in == 2) and np.all(c_out == 1)
+
+
+@pytest.mark.parametrize("variant", ["interpolated", "sector"])
+def test_flag_symmetric_step_tie(variant):
+    """Bit 1: an exactly symmetric step has equal strengths at c-1 and c (the
+    two pixels flanking it); each sees the tie on a different side (c-1
+    ahead, c behind), so both carry bit 1 and no other column does."""
+    fn = oracle.classify_f32 if variant == "interpolated" else oracle.classify_f32_sector
+    X = _step_image(60.0, 160.0)
+    cls, M, amb, _ = fn(X, 1.4, 3, 1.0, 2.0, False, TOL_PIN)
+    tied = (amb & 2) != 0
+    assert np.all(tied[:, 19]) and np.all(tied[:, 20])
+    tied[:, 19:21] = False
+    assert not tied.any()
+    assert np.all(cls[:, 19] == 2) and np.all(cls[:, 20] == 0)  # raster tie rule
+
+
+@pytest.mark.parametrize("variant", ["interpolated", "sector"])
+def test_flag_near_tie_band(variant):
+    """Bit 1 band: one column of value m at the step makes M(c-1) / M(c) =
+    1 + delta with delta = (m - b)(g_0 - g_2) / ((b - a)(g_0 + g_1)) (closed
+    form, rows constant).  delta = tol/2 sets bit 1 at both pixels; 3 tol
+    leaves it clear."""
+    g = _library_taps(1.4, 3)
+    a, b = 60.0, 160.0
+    fn = oracle.classify_f32 if variant == "interpolated" else oracle.classify_f32_sector
+    for target, expect in ((TOL_PIN / 2, True), (3 * TOL_PIN, False)):
+        m = np.float32(b + (b - a) * target * (g[0] + g[1]) / (g[0] - g[2]))
+        delta = (float(m) - b) * (g[0] - g[2]) / ((b - a) * (g[0] + g[1]))  # after fp32 rounding
+        assert abs(delta - target) < 0.05 * target
+        X = _step_image(a, b, mid=m)
+        _, M, amb, _ = fn(X, 1.4, 3, 1.0, 2.0, False, TOL_PIN)
+        assert np.allclose(M[:, 19] / M[:, 20], 1 + delta, rtol=1e-9)
+        assert np.all(((amb[:, 19] & 2) != 0) == expect)
+        assert np.all(((amb[:, 20] & 2) != 0) == expect)
+
+
+@pytest.mark.parametrize("base_deg", [22.5, 67.5])
+def test_flag_sector_boundary_band(base_deg):
+    """Bit 3 of the four-sector variant: on a plane s (cos t x + sin t y) the
+    interior gradient is (8 s cos t, 8 s sin t), so the distance to the sector
+    boundary at base_deg is |ay - tan(base) ax| / M = |sin(t - base)| / cos(base)
+    exactly.  The flag band is 4 tol; the plane is placed at 1/2 and 2 band
+    widths on either side of the boundary."""
+    tol = 1e-3  # wide enough that the fp32 rounding of the plane is negligible
+    th0 = np.deg2rad(base_deg)
+    y, x = np.mgrid[0:48, 0:48]
+    inner = np.s_[8:-8, 8:-8]
+    for rho, expect in ((2 * tol, True), (8 * tol, False)):
+        for side in (1, -1):
+            eps = side * np.arcsin(rho * np.cos(th0))
+            t = th0 + eps
+            X = (10.0 + 1.7 * (np.cos(t) * x + np.sin(t) * y)).astype(np.float32)
+            cls, M, amb, _ = oracle.classify_f32_sector(X, 1.4, 3, 1.0, 2.0, False, tol)
+            gx, gy = oracle.sobel_f64(oracle.gauss_blur(X.astype(np.float64), 1.4, 3))
+            ang = np.arctan2(gy[inner], gx[inner])
+            assert np.allclose(ang, t, atol=1e-5)  # the plane's gradient direction
+            assert np.all(((amb[inner] & 8) != 0) == expect), (base_deg, rho, side)
+
+
+@pytest.mark.parametrize("tol", [0.3, 0.05])
+def test_flags_equal_library_at_wide_tolerance(tol):
+    """Bits 0 and 1 against their definitions evaluated on the independent
+    scipy pipeline, at tolerances wide enough that readings such as a band of
+    tol * M instead of tol * t, or one side of the tie only, flag visibly
+    different pixel sets.  Pixels whose library margin is within 1e-9 of a
+    band edge are left out (fp64 rounding)."""
+    X = workloads.natural_u8(96, 128, seed=11).astype(np.float32)
+    _, M, amb, mx = oracle.classify_f32(X, 1.4, 3, 0.05, 0.15, True, tol)
+    _, eM, mf, mb = _float_classes_library(X)
+    lo, hi = 0.05 * eM.max(), 0.15 * eM.max()
+    e0 = np.abs(eM - lo) - tol * lo, np.abs(eM - hi) - tol * hi
+    b0 = (e0[0] <= 0) | (e0[1] <= 0)
+    safe0 = (np.abs(e0[0]) > 1e-9 * lo) & (np.abs(e0[1]) > 1e-9 * hi)
+    e1 = np.abs(eM - mf) - tol * eM, np.abs(eM - mb) - tol * eM
+    b1 = (eM > 0) & ((e1[0] <= 0) | (e1[1] <= 0))
+    safe1 = (np.abs(e1[0]) > 1e-9 * eM) & (np.abs(e1[1]) > 1e-9 * eM)
+    safe1 &= eM > 1e-9 * eM.max()  # M = 0 in exact arithmetic, ~1e-14 in the library's
+    assert b0.sum() > 100 and b1.sum() > 100
+    assert np.array_equal(((amb & 1) != 0)[safe0], b0[safe0])
+    assert np.array_equal(((amb & 2) != 0)[safe1], b1[safe1])
+    assert safe0.mean() > 0.99 and safe1.mean() > 0.95
+
+
+def test_kernel_integer_sector_rule_exhaustive():
+    """The integer kernel decides the sector without atan2: horizontal iff
+    408 ay < 169 ax, vertical iff 408 ax < 169 ay, else the diagonal by the
+    sign of Gx Gy (169/408 is a convergent of sqrt(2) - 1 whose error is
+    below the closest approach of any pair with |Gx|, |Gy| <= 1020 to the
+    boundary).  That rule, restated here, equals the oracle's atan2 sector on
+    every gradient of the Sobel range."""
+    r = np.arange(-1020, 1021, dtype=np.int64)
+    gx, gy = [a.ravel() for a in np.meshgrid(r, r, indexing="ij")]
+    keep = (gx != 0) | (gy != 0)
+    gx, gy = gx[keep], gy[keep]
+    ax, ay = np.abs(gx), np.abs(gy)
+    rule = np.where(408 * ay < 169 * ax, 0,
+                    np.where(408 * ax < 169 * ay, 2, np.where(gx * gy > 0, 1, 3)))
+    assert np.array_equal(oracle.sector(gx.astype(np.int32), gy.astype(np.int32)),
+                          rule.astype(np.uint8))
