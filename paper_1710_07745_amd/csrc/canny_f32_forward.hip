@@ -23,12 +23,18 @@
 // the thresholds from that word and writes the class map.  The walk, the
 // expensive part, therefore runs once per image in both cases.
 //
-// Accuracy: every stage before the strength is linear, and Sobel ignores a
-// constant offset, so the walk filters X - c instead of X, with c the
-// midpoint of the value range of the wave's first input row.  The fp32
-// accumulations then round at a magnitude no larger than the image's value
-// range (about half of it when that row spans the range), and a constant
-// image gives exactly zero.
+// Accuracy: every stage before the strength is linear, so the walk filters
+// X - off(x) instead of X, with off a line in the column, c + a x', taken
+// from the wave's first input row (x' = column within the wave's window; a
+// is 0 unless the row shows a trend across the strip).  The normalised
+// symmetric Gaussian maps a line to itself (times the square of the taps'
+// sum S), so the Sobel terms of the line are known exactly: nothing in y,
+// and 8 S a in x, which is added back to Gx.  c and a lie on a power-of-two
+// grid on which every off(x') is an exact fp32 value, so the subtraction is
+// the only rounding the offset adds.  The fp32 accumulations then round at
+// the magnitude of what the line does not explain (local contrast, not the
+// image's level or a trend across the strip), and a constant image gives
+// exactly zero.
 //
 // Suppression interpolates along the continuous gradient direction: with
 // t = min(|Gx|,|Gy|) / max(|Gx|,|Gy|) and same = (Gx*Gy > 0),
@@ -106,6 +112,57 @@ struct WalkPlan {
     int k, nb;           // interior / bottom border blocks per interior strip
 };
 
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+    return v;  // a butterfly: every lane adds the same two operands per step
+}
+
+// The offset line off(x') = c + a x' of a wave, x' = 4 lane + k in 0..255,
+// from the wave's first input row.  Two candidates: the constant midpoint of
+// the row's range (a = 0), and a line with the least-squares slope and the
+// midpoint of what it leaves.  The line is taken only where it at least
+// halves the row's largest deviation from the offset: a trend across the
+// strip.  A tilt fitted to ordinary content would help the first row and
+// hurt the rows below it.  A line is rounded to the grid q = 2^(e - 21) with
+// |c| + 255 |a| < 2^e; then |c|, |a x'| and |off| stay below 2^22 q, so
+// fmaf(a, x', c) is exact.  Any line gives the same result in exact
+// arithmetic (its Gaussian and Sobel terms are added back); the choice only
+// keeps the filtered values small.
+struct OffsetLine { float a, c; };
+
+__device__ __forceinline__ OffsetLine offset_line(const F4& r0, int lane) {
+    float sx = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) sx = fmaf((float)(4 * lane + k) - 127.5f, r0.v[k], sx);
+    const float lo = wave_min(fminf(fminf(r0.v[0], r0.v[1]), fminf(r0.v[2], r0.v[3])));
+    const float hi = wave_max(fmaxf(fmaxf(r0.v[0], r0.v[1]), fmaxf(r0.v[2], r0.v[3])));
+    sx = wave_sum(sx);
+    const float a = sx * (1.0f / 1398080.0f);  // sum of (x' - 127.5)^2, x' = 0..255
+    float rl = r0.v[0], rh = r0.v[0];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float e = fmaf(-a, (float)(4 * lane + k), r0.v[k]);
+        rl = k ? fminf(rl, e) : e;
+        rh = k ? fmaxf(rh, e) : e;
+    }
+    rl = wave_min(rl);
+    rh = wave_max(rh);
+    OffsetLine ol{0.0f, 0.5f * lo + 0.5f * hi};
+    const float c = 0.5f * rl + 0.5f * rh;
+    const float A = fabsf(c) + 255.0f * fabsf(a);
+    if (rh - rl <= 0.5f * (hi - lo) && A > 1e-30f && A < 1e30f) {
+        int e;
+        (void)frexpf(A, &e);  // A < 2^e
+        const float q = ldexpf(1.0f, e - 21), inv_q = ldexpf(1.0f, 21 - e);
+        ol.a = rintf(a * inv_q) * q;
+        ol.c = rintf(c * inv_q) * q;
+    }
+    ol.a = bc<float>(__builtin_amdgcn_readfirstlane(bc<int>(ol.a)));
+    ol.c = bc<float>(__builtin_amdgcn_readfirstlane(bc<int>(ol.c)));
+    return ol;
+}
+
 template <int R, int RR, bool SIGNED, bool SECTOR, bool EDGE>
 __device__ __forceinline__ void f32_walk(const F32FwdArgs& a, int X0, int Y0, int lane, int fast_ok) {
     static_assert(!(SIGNED && SECTOR), "the four-sector variant classifies in the walk");
@@ -164,15 +221,24 @@ __device__ __forceinline__ void f32_walk(const F32FwdArgs& a, int X0, int Y0, in
 #pragma unroll
     for (int k = 0; k < PF && k < NI; ++k) in[k] = fetch(k);
 
-    // offset c subtracted from every input value (see the file comment)
-    float off;
-    {
-        const F4& r0 = in[0];
-        const float lo = wave_min(fminf(fminf(r0.v[0], r0.v[1]), fminf(r0.v[2], r0.v[3])));
-        const float hi = wave_max(fmaxf(fmaxf(r0.v[0], r0.v[1]), fmaxf(r0.v[2], r0.v[3])));
-        off = 0.5f * lo + 0.5f * hi;
-    }
-    off = bc<float>(__builtin_amdgcn_readfirstlane(bc<int>(off)));  // wave-uniform
+    // offset plane subtracted from every input value (see the file comment)
+    const OffsetLine ol = offset_line(in[0], lane);
+    float off[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) off[k] = fmaf(ol.a, (float)(4 * lane + k), ol.c);  // exact
+    // the blurred window is B - S (c + a x') with S the square of the taps'
+    // exact sum, so every horizontal difference of it lacks 2 S a, and Gx
+    // (1, 2, 1 of them) lacks 8 S a; in border strips the replicated columns
+    // of B need S a (edge - x) on top of the copied edge value
+    float gsum = g[0];
+#pragma unroll
+    for (int j = 1; j <= R; ++j) gsum = fmaf(2.0f, g[j], gsum);
+    const float Sa = gsum * gsum * ol.a;
+    const float gx_fix = 8.0f * Sa;
+    float bfix[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        bfix[k] = bd.outL[k] ? Sa * (float)(-(c0 + k)) : (bd.outR[k] ? Sa * (float)(W - 1 - (c0 + k)) : 0.0f);
 
     // per-row values, indexed by relative row (compile-time indices only)
     F4 Bv[NI], dxv[NI], sxv[NI], gxv[NI], gyv[NI];
@@ -184,7 +250,7 @@ __device__ __forceinline__ void f32_walk(const F32FwdArgs& a, int X0, int Y0, in
         if (i + PF < NI) in[i + PF] = fetch(i + PF);
         if (i < NI) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) in[i].v[q] -= off;
+            for (int q = 0; q < 4; ++q) in[i].v[q] -= off[q];
         }
 
         // ---- Step 3 + thresholds: suppression of row tD
@@ -295,7 +361,7 @@ __device__ __forceinline__ void f32_walk(const F32FwdArgs& a, int X0, int Y0, in
             F4 M;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                const float gx = fmaf(2.0f, dxv[tC].v[k], dm.v[k] + dp.v[k]);
+                const float gx = fmaf(2.0f, dxv[tC].v[k], dm.v[k] + dp.v[k]) + gx_fix;
                 const float gy = sp.v[k] - sm.v[k];
                 gxv[tC].v[k] = gx;
                 gyv[tC].v[k] = gy;
@@ -344,7 +410,11 @@ __device__ __forceinline__ void f32_walk(const F32FwdArgs& a, int X0, int Y0, in
                 for (int j = 1; j <= R; ++j) acc = fmaf(g[j], ext[k + R - j] + ext[k + R + j], acc);
                 Bv[tA].v[k] = acc;
             }
-            if (EDGE) fix_cols(Bv[tA], bd);
+            if (EDGE) {
+                fix_cols(Bv[tA], bd);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) Bv[tA].v[k] += bfix[k];
+            }
         }
     }
 

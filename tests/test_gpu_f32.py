@@ -79,12 +79,14 @@ def test_float_radii(canny, R):
     of the error measure) shrinks while the fp32 rounding of the blur stays at
     about eps*255 per tap; the bound used here, 16*eps*255*(2R+1)/floor with
     eps = 2^-24, is that rounding summed over the 2R+1 taps of each pass and
-    amplified by Sobel's 8, and never tighter than 1e-5."""
+    amplified by Sobel's 8, and never tighter than 1e-5.  That bound applies
+    to the strength only: the set of excused pixels (decisions within the
+    tolerance of a threshold or a suppression tie) stays at 1e-5."""
     X = workloads.natural_u8(97, 301, seed=R).astype(np.float32)
     sigma = 0.5 + 0.4 * R
     _, _, _, omx = oracle.classify_f32(X, sigma, R)
     tol = max(TOL, 16 * 2.0 ** -24 * 255 * (2 * R + 1) / (0.05 * omx))
-    check_float(canny, X, sigma=sigma, R=R, tol=tol)
+    check_float(canny, X, sigma=sigma, R=R, tol=tol, excuse_tol=TOL, label=f"radius {R}")
 
 
 @pytest.mark.parametrize("H", [1, 2, 3, 5, 8, 13, 33, 40])
@@ -289,10 +291,12 @@ def test_float_edges_only_absolute_with_max(canny):
 
 # ---- four-sector variant (absolute thresholds, one launch) -------------------
 
-def check_sector(canny, X, sigma=1.4, R=3, low=None, high=None, tol=TOL):
+def check_sector(canny, X, sigma=1.4, R=3, low=None, high=None, tol=TOL, label=""):
     """Classes equal the four-sector oracle's on every pixel it does not flag
     (threshold, suppression near-tie, sector boundary); strength within the
-    float tolerance; edges = breadth-first search on the GPU's classes."""
+    float tolerance; edges = breadth-first search on the GPU's classes.
+    Prints the achieved strength error, the excused pixels, how many of them
+    differ, and how many would be excused at 1e-5."""
     H, W = X.shape
     if low is None:
         lo, hi = absolute_like_relative(X, sigma, R)
@@ -305,9 +309,14 @@ def check_sector(canny, X, sigma=1.4, R=3, low=None, high=None, tol=TOL):
     c = unpack_classes(cls.cpu().numpy(), H, W)
     oc, oM, amb, omx = oracle.classify_f32_sector(X, sigma, R, lo, hi, False, tol)
     err = np.abs(mag.cpu().numpy() - oM) / np.maximum(np.maximum(oM, 0.05 * omx), 1e-30)
-    assert err.max() <= tol or omx == 0.0, f"strength error {err.max():.3g}"
     unamb = (amb & 11) == 0
     diff = (c != oc) & unamb
+    narrow = int(((oracle.classify_f32_sector(X, sigma, R, lo, hi, False, TOL)[2] & 11) != 0).sum()) \
+        if tol != TOL else int((~unamb).sum())
+    print(f"[sector {label} {H}x{W} R={R}] strength error {err.max():.3g} (bound {tol:.3g}); "
+          f"excused pixels {int((~unamb).sum())} ({narrow} at 1e-5), of which differ "
+          f"{int(((c != oc) & ~unamb).sum())}", flush=True)
+    assert err.max() <= tol or omx == 0.0, f"strength error {err.max():.3g}"
     assert diff.sum() == 0, f"{diff.sum()} class mismatches at {np.argwhere(diff)[:5].tolist()}"
     be, _ = oracle.hysteresis(c)
     assert np.array_equal(e.cpu().numpy(), be)
@@ -336,7 +345,7 @@ def test_sector_radii(canny, R):
     sigma = 0.5 + 0.4 * R
     _, _, _, omx = oracle.classify_f32(X, sigma, R)
     tol = max(TOL, 16 * 2.0 ** -24 * 255 * (2 * R + 1) / (0.05 * omx))
-    check_sector(canny, X, sigma=sigma, R=R, tol=tol)
+    check_sector(canny, X, sigma=sigma, R=R, tol=tol, label=f"radius {R}")
 
 
 def test_sector_ragged_and_4096(canny):
