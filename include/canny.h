@@ -46,7 +46,9 @@ enum {
     CANNY_ERR_INVALID = 1,     /* bad argument; nothing enqueued        */
     CANNY_ERR_WORKSPACE = 2,   /* workspace missing or too small        */
     CANNY_ERR_HIP = 3,         /* the HIP runtime reported an error      */
-    CANNY_ERR_UNSUPPORTED = 4  /* device is not gfx950                  */
+    CANNY_ERR_UNSUPPORTED = 4, /* device is not gfx950                  */
+    CANNY_ERR_TOO_LARGE = 5    /* canny_u8_noalloc: image needs more than
+                                  CANNY_NOALLOC_SCRATCH_BYTES of scratch */
 };
 
 /* Human-readable name of a status code (static string, never NULL). */
@@ -87,6 +89,28 @@ size_t canny_u8_workspace_bytes(int H, int W);
 int canny_u8(const uint8_t* in, int64_t in_pitch, int H, int W, int32_t low, int32_t high,
              uint8_t* edges, int64_t edges_pitch, uint8_t* class2, void* ws, size_t ws_bytes,
              void* stream);
+
+/* ---------------------------------------------------------------------
+ * canny_u8 without a workspace argument and without any allocation, for
+ * callers that cannot allocate device memory: code being recorded into a
+ * HIP graph, tight serving loops, and hosts that forbid hipMalloc.
+ *
+ * Same operator, arguments, outputs and validation as canny_u8, minus
+ * ws / ws_bytes.  The workspace is a file-scope device array of
+ * CANNY_NOALLOC_SCRATCH_BYTES bytes inside the library: one copy per GPU the
+ * library runs on, loaded with the library's code and held until the process
+ * ends.  The call makes no hipMalloc, hipFree or other allocating call; the
+ * first call on a device looks up that device's copy (hipGetSymbolAddress).
+ * Images with canny_u8_workspace_bytes(H, W) > CANNY_NOALLOC_SCRATCH_BYTES
+ * return CANNY_ERR_TOO_LARGE before anything is enqueued.
+ * Every call on one GPU uses that GPU's single array, and it keeps the last
+ * call's contents (nothing in it needs clearing: each call writes what it
+ * reads).  Calls that can overlap on one GPU (different streams, or threads)
+ * race on it and give wrong results; serialise them.
+ */
+#define CANNY_NOALLOC_SCRATCH_BYTES (32u << 20)
+int canny_u8_noalloc(const uint8_t* in, int64_t in_pitch, int H, int W, int32_t low, int32_t high,
+                     uint8_t* edges, int64_t edges_pitch, uint8_t* class2, void* stream);
 
 /* ---------------------------------------------------------------------
  * Hysteresis alone (Step 4 connectivity) on a caller-provided class map.

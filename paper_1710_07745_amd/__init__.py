@@ -20,7 +20,7 @@ from . import _lib
 from ._lib import CannyError, check, lib
 
 __all__ = [
-    "canny_u8", "canny_f32", "canny_f32_sector", "VideoStream", "hysteresis", "class_pitch", "u8_workspace_bytes", "f32_workspace_bytes",
+    "canny_u8", "canny_u8_noalloc", "canny_f32", "canny_f32_sector", "VideoStream", "hysteresis", "class_pitch", "u8_workspace_bytes", "f32_workspace_bytes",
     "BatchPlan", "mag_forward", "mag_backward", "CannyMagnitude", "canny_magnitude",
     "CannyError", "StageTiming",
 ]
@@ -83,6 +83,21 @@ def canny_u8(img: torch.Tensor, low: int = 40, high: int = 100, *, edges: Option
     check("canny_u8", st)
     if return_classes:
         return (edges if with_edges else None), class_map
+    return edges
+
+
+def canny_u8_noalloc(img: torch.Tensor, low: int = 40, high: int = 100, *, edges: torch.Tensor,
+                     class_map: Optional[torch.Tensor] = None):
+    """canny_u8 through the allocation-free entry point: the caller passes the
+    output buffers; the workspace is the library's static device scratch
+    (images needing more than CANNY_NOALLOC_SCRATCH_BYTES raise).  This
+    function allocates nothing either."""
+    _check_image(img, torch.uint8)
+    H, W = img.shape
+    st = lib().canny_u8_noalloc(img.data_ptr(), img.stride(0), H, W, int(low), int(high),
+                                _ptr(edges), edges.stride(0) if edges is not None else 0,
+                                _ptr(class_map), _stream(img))
+    check("canny_u8_noalloc", st)
     return edges
 
 

@@ -17,6 +17,8 @@ CANNY_ERR_INVALID = 1
 CANNY_ERR_WORKSPACE = 2
 CANNY_ERR_HIP = 3
 CANNY_ERR_UNSUPPORTED = 4
+CANNY_ERR_TOO_LARGE = 5
+CANNY_NOALLOC_SCRATCH_BYTES = 32 << 20  # include/canny.h
 
 P = C.c_void_p
 i32 = C.c_int32
@@ -31,6 +33,7 @@ SIGNATURES = {
     "canny_class_pitch": (i64, [C.c_int]),
     "canny_u8_workspace_bytes": (sz, [C.c_int, C.c_int]),
     "canny_u8": (C.c_int, [P, i64, C.c_int, C.c_int, i32, i32, P, i64, P, P, sz, P]),
+    "canny_u8_noalloc": (C.c_int, [P, i64, C.c_int, C.c_int, i32, i32, P, i64, P, P]),
     "canny_hysteresis_workspace_bytes": (sz, [C.c_int, C.c_int]),
     "canny_hysteresis": (C.c_int, [P, C.c_int, C.c_int, P, i64, P, sz, P]),
     "canny_f32_workspace_bytes": (sz, [C.c_int, C.c_int]),

@@ -70,11 +70,12 @@ const char* canny_status_string(int status) {
         case CANNY_ERR_WORKSPACE: return "workspace missing or too small";
         case CANNY_ERR_HIP: return "HIP runtime error";
         case CANNY_ERR_UNSUPPORTED: return "unsupported device (gfx950 required)";
+        case CANNY_ERR_TOO_LARGE: return "image too large for the allocation-free entry point's scratch";
         default: return "unknown status";
     }
 }
 
-int canny_abi_version(void) { return 4; }
+int canny_abi_version(void) { return 5; }
 
 int64_t canny_class_pitch(int W) { return class_pitch(W); }
 
@@ -83,19 +84,25 @@ size_t canny_u8_workspace_bytes(int H, int W) {
     return class_bytes(H, W) + hyst_workspace_bytes(H, W, hyst_tile_rows_default());
 }
 
-int canny_u8(const uint8_t* in, int64_t in_pitch, int H, int W, int32_t low, int32_t high,
-             uint8_t* edges, int64_t edges_pitch, uint8_t* class2, void* ws, size_t ws_bytes,
-             void* stream) {
-    if (!in || !size_ok(H, W) || in_pitch < W || low < 0 || low > high) return CANNY_ERR_INVALID;
-    if (edges && edges_pitch < W) return CANNY_ERR_INVALID;
-    if (class2 && ((uintptr_t)class2 % 4)) return CANNY_ERR_INVALID;
-    const size_t nin = image_bytes(H, in_pitch, W, 1);
-    if (edges && overlaps(in, nin, edges, image_bytes(H, edges_pitch, W, 1))) return CANNY_ERR_INVALID;
-    if (class2 && overlaps(in, nin, class2, (size_t)H * class_pitch(W))) return CANNY_ERR_INVALID;
-    const size_t need = canny_u8_workspace_bytes(H, W);
-    if (!ws || ws_bytes < need || ((uintptr_t)ws % 256)) return CANNY_ERR_WORKSPACE;
-    if (!device_ok()) return CANNY_ERR_UNSUPPORTED;
+}  // extern "C"
 
+namespace canny {
+
+static bool u8_args_ok(const uint8_t* in, int64_t in_pitch, int H, int W, int32_t low, int32_t high,
+                       const uint8_t* edges, int64_t edges_pitch, const uint8_t* class2) {
+    if (!in || !size_ok(H, W) || in_pitch < W || low < 0 || low > high) return false;
+    if (edges && edges_pitch < W) return false;
+    if (class2 && ((uintptr_t)class2 % 4)) return false;
+    const size_t nin = image_bytes(H, in_pitch, W, 1);
+    if (edges && overlaps(in, nin, edges, image_bytes(H, edges_pitch, W, 1))) return false;
+    if (class2 && overlaps(in, nin, class2, (size_t)H * class_pitch(W))) return false;
+    return true;
+}
+
+// canny_u8 after validation: the forward and the hysteresis passes on the
+// workspace ws (canny_u8_workspace_bytes(H, W) bytes, 256-byte aligned).
+static int u8_run(const uint8_t* in, int64_t in_pitch, int H, int W, int32_t low, int32_t high,
+                  uint8_t* edges, int64_t edges_pitch, uint8_t* class2, void* ws, void* stream) {
     hipStream_t s = static_cast<hipStream_t>(stream);
     char* w = static_cast<char*>(ws);
     U8FwdArgs f;
@@ -123,6 +130,60 @@ int canny_u8(const uint8_t* in, int64_t in_pitch, int H, int W, int32_t low, int
     const int T = hyst_tile_rows_default();
     hyst_carve(w + class_bytes(H, W), H, W, T, h);
     return status_of(timed_hysteresis(h, T, s));
+}
+
+// Scratch of canny_u8_noalloc: one array per GPU the library runs on, held
+// until the process ends.  In host code `scratch` names a host-side stand-in;
+// the device address comes from hipGetSymbolAddress, once per device, and is
+// the only form of it that host code passes on.
+static __device__ __align__(256) unsigned char scratch[CANNY_NOALLOC_SCRATCH_BYTES];
+
+static void* scratch_address(int* status) {
+    static std::mutex mu;
+    static void* addr[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+        *status = CANNY_ERR_HIP;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+            *status = CANNY_ERR_HIP;
+            return nullptr;
+        }
+        addr[dev] = p;
+    }
+    return addr[dev];
+}
+
+}  // namespace canny
+
+extern "C" {
+
+int canny_u8(const uint8_t* in, int64_t in_pitch, int H, int W, int32_t low, int32_t high,
+             uint8_t* edges, int64_t edges_pitch, uint8_t* class2, void* ws, size_t ws_bytes,
+             void* stream) {
+    if (!u8_args_ok(in, in_pitch, H, W, low, high, edges, edges_pitch, class2)) return CANNY_ERR_INVALID;
+    const size_t need = canny_u8_workspace_bytes(H, W);
+    if (!ws || ws_bytes < need || ((uintptr_t)ws % 256)) return CANNY_ERR_WORKSPACE;
+    if (!device_ok()) return CANNY_ERR_UNSUPPORTED;
+    return u8_run(in, in_pitch, H, W, low, high, edges, edges_pitch, class2, ws, stream);
+}
+
+int canny_u8_noalloc(const uint8_t* in, int64_t in_pitch, int H, int W, int32_t low, int32_t high,
+                     uint8_t* edges, int64_t edges_pitch, uint8_t* class2, void* stream) {
+    if (!u8_args_ok(in, in_pitch, H, W, low, high, edges, edges_pitch, class2)) return CANNY_ERR_INVALID;
+    if (canny_u8_workspace_bytes(H, W) > (size_t)CANNY_NOALLOC_SCRATCH_BYTES) return CANNY_ERR_TOO_LARGE;
+    if (!device_ok()) return CANNY_ERR_UNSUPPORTED;
+    int status = CANNY_OK;
+    void* ws = scratch_address(&status);
+    if (!ws) return status;
+    // the passes write every workspace word they later read (class map,
+    // border names, union-find entries of this call's components, pending
+    // masks), so nothing left by an earlier call needs clearing
+    return u8_run(in, in_pitch, H, W, low, high, edges, edges_pitch, class2, ws, stream);
 }
 
 size_t canny_hysteresis_workspace_bytes(int H, int W) {

@@ -47,7 +47,7 @@ def test_status_strings_and_pitch(lib):
     assert lib.canny_status_string(0) == b"ok"
     assert lib.canny_status_string(2).startswith(b"workspace")
     assert lib.canny_status_string(99) == b"unknown status"
-    assert lib.canny_abi_version() == 4
+    assert lib.canny_abi_version() == 5
     for W, p in [(0, 0), (1, 4), (4, 4), (5, 4), (16, 4), (17, 8), (4096, 1024), (4097, 1028)]:
         assert lib.canny_class_pitch(W) == p, W
 
@@ -74,6 +74,22 @@ def test_host_validation_u8(lib):
     assert lib.canny_u8(FAKE, 8, 8, 8, 10, 20, None, 8, C.c_void_p(0x2002), ws, n, None) == 1  # align
     assert lib.canny_u8(FAKE, 8, 8, 8, 10, 20, None, 8, None, None, n, None) == 2
     assert lib.canny_u8(FAKE, 8, 8, 8, 10, 20, None, 8, None, ws, 16, None) == 2
+
+
+def test_host_validation_u8_noalloc(lib):
+    """The allocation-free entry point validates like canny_u8 and rejects
+    images whose workspace exceeds its static scratch before any device work."""
+    from paper_1710_07745_amd import _lib
+    f = lib.canny_u8_noalloc
+    assert f(None, 8, 8, 8, 10, 20, None, 8, None, None) == 1
+    assert f(FAKE, 7, 8, 8, 10, 20, None, 8, None, None) == 1  # pitch < W
+    assert f(FAKE, 8, 8, 8, 30, 20, None, 8, None, None) == 1  # low > high
+    assert f(FAKE, 8, 8, 8, 10, 20, C.c_void_p(0x1002), 8, None, None) == 1  # alias
+    assert f(FAKE, 8, 8, 8, 10, 20, None, 8, C.c_void_p(0x2002), None) == 1  # align
+    H = W = 8192
+    assert lib.canny_u8_workspace_bytes(H, W) > _lib.CANNY_NOALLOC_SCRATCH_BYTES
+    assert f(FAKE, W, H, W, 10, 20, None, W, None, None) == _lib.CANNY_ERR_TOO_LARGE
+    assert lib.canny_status_string(_lib.CANNY_ERR_TOO_LARGE).startswith(b"image too large")
 
 
 def test_host_validation_f32(lib):
