@@ -72,6 +72,9 @@ def _load():
         "oracle_classify_f32_sector": (l, [P, i, i, d, i, d, d, i, d, P, P, P, P]),
         "oracle_mag_forward": (None, [P, i, i, d, i, P]),
         "oracle_mag_backward": (None, [P, i, i, d, i, P, P, P]),
+        "oracle_laplace_i32": (None, [P, i, i, P]),
+        "oracle_zero_crossings": (l, [P, i, i, i, P]),
+        "oracle_log_u8": (l, [P, i, i, i, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -244,6 +247,41 @@ def mag_backward(I, sigma, gM, R=9):
 
 
 # ---- the paper's parallel design on the CPU (baseline, not an oracle) ------
+
+# ---- Laplacian zero-crossing detector (the introduction's Laplace operator) ----
+
+def laplace_i32(B):
+    """L = B(x-1) + B(x+1) + B(y-1) + B(y+1) - 4 B with replicate borders."""
+    B = _u8(B)
+    H, W = B.shape
+    L = np.empty((H, W), np.int32)
+    _load().oracle_laplace_i32(_p(B), H, W, _p(L))
+    return L
+
+
+def zero_crossings(L, t):
+    """Edges (255 / 0) at the zero crossings of L: between 4-neighbours of
+    strictly opposite signs with |L(p) - L(q)| >= t (marked on the pixel of
+    the pair nearer the zero, the earlier one on a tie), and at zeros whose
+    opposite neighbours (left/right or up/down) have strictly opposite signs
+    with a difference >= t."""
+    L = np.ascontiguousarray(L, dtype=np.int32)
+    H, W = L.shape
+    e = np.empty((H, W), np.uint8)
+    _load().oracle_zero_crossings(_p(L), H, W, int(t), _p(e))
+    return e
+
+
+def log_u8(img, t):
+    """The whole detector on a uint8 image: binomial blur (Step 1 of the
+    integer path), Laplacian, zero crossings.  Returns (edges, L)."""
+    img = _u8(img)
+    H, W = img.shape
+    e = np.empty((H, W), np.uint8)
+    L = np.empty((H, W), np.int32)
+    _load().oracle_log_u8(_p(img), H, W, int(t), _p(e), _p(L))
+    return e, L
+
 
 def _load_pd():
     global _pd_lib

@@ -511,3 +511,87 @@ void oracle_mag_backward(const double* I, int H, int W, double sigma, int R, con
     free(g); free(dg); free(T); free(B); free(Gx); free(Gy); free(dB); free(dT);
     free(Tp); free(Bs); free(tmp);
 }
+
+/* ------------------------------------------------------------------------
+ * Laplacian zero-crossing detector (the comparator the paper's introduction
+ * sets Canny against, Laplace(f) = f_xx + f_yy), integer path
+ * ---------------------------------------------------------------------- */
+
+/* The Laplace operator on the Step-1-filtered image B (the same 5x5 binomial
+ * as the integer Canny path), as the sum of the second central differences
+ * along each axis, with clamped (replicate-border) reads:
+ *   L(y,x) = [B(y,x-1) - 2 B(y,x) + B(y,x+1)] + [B(y-1,x) - 2 B(y,x) + B(y+1,x)]. */
+void oracle_laplace_i32(const uint8_t* B, int H, int W, int32_t* L) {
+    for (int y = 0; y < H; ++y) {
+        for (int x = 0; x < W; ++x) {
+            int c = B[(long)y * W + x];
+            int dxx = (int)B[(long)y * W + clampi(x - 1, W)] - 2 * c + (int)B[(long)y * W + clampi(x + 1, W)];
+            int dyy = (int)B[(long)clampi(y - 1, H) * W + x] - 2 * c + (int)B[(long)clampi(y + 1, H) * W + x];
+            L[(long)y * W + x] = dxx + dyy;
+        }
+    }
+}
+
+/* Zero crossings of L, two cases.
+ *  (a) Between two pixels: every pair of 4-neighbours (p, q), q the right or
+ *      the lower neighbour of p, both inside the image, is visited once; the
+ *      pair crosses iff L(p) and L(q) have strictly opposite signs (one > 0,
+ *      the other < 0) and |L(p) - L(q)| >= t.  The crossing is marked on the
+ *      one whose |L| is smaller (the one nearer the zero), on p when they are
+ *      equal (the earlier pixel in raster order).
+ *  (b) At a pixel: p with L(p) = 0 is marked iff its left and right
+ *      neighbours, or its upper and lower neighbours (all inside the image),
+ *      have strictly opposite signs with |difference| >= t.
+ * Zeros never cross in (a), so a Laplacian that returns to 0 (the tail of a
+ * blurred step) marks nothing; a zero run of two or more pixels between
+ * opposite signs marks nothing either.
+ * edges: 255 on marked pixels, 0 elsewhere.  Returns the number of marked
+ * pixels. */
+static int strictly_opposite(int a, int b) { return (a > 0 && b < 0) || (a < 0 && b > 0); }
+
+long oracle_zero_crossings(const int32_t* L, int H, int W, int t, uint8_t* edges) {
+    long n = (long)H * W, count = 0;
+    memset(edges, 0, n);
+    for (int y = 0; y < H; ++y) {
+        for (int x = 0; x < W; ++x) {
+            long p = (long)y * W + x;
+            /* (a) the pairs (p, right) and (p, below) */
+            for (int dir = 0; dir < 2; ++dir) {
+                int yy = y + (dir == 1), xx = x + (dir == 0);
+                if (yy >= H || xx >= W) continue;
+                long q = (long)yy * W + xx;
+                int lp = L[p], lq = L[q];
+                if (!strictly_opposite(lp, lq) || abs(lp - lq) < t) continue;
+                edges[abs(lp) <= abs(lq) ? p : q] = 255;
+            }
+            /* (b) a zero between strictly opposite neighbours */
+            if (L[p] == 0) {
+                if (x >= 1 && x + 1 < W) {
+                    int a = L[p - 1], b = L[p + 1];
+                    if (strictly_opposite(a, b) && abs(a - b) >= t) edges[p] = 255;
+                }
+                if (y >= 1 && y + 1 < H) {
+                    int a = L[p - W], b = L[p + W];
+                    if (strictly_opposite(a, b) && abs(a - b) >= t) edges[p] = 255;
+                }
+            }
+        }
+    }
+    for (long k = 0; k < n; ++k) count += edges[k] != 0;
+    return count;
+}
+
+/* The whole detector: B = Step 1 (5x5 binomial, one rounding), L = Laplace(B),
+ * edges = zero crossings of L with slope threshold t.  L_out may be NULL. */
+long oracle_log_u8(const uint8_t* I, int H, int W, int t, uint8_t* edges, int32_t* L_out) {
+    long n = (long)H * W;
+    uint8_t* B = (uint8_t*)malloc(n > 0 ? n : 1);
+    int32_t* L = (int32_t*)malloc((n > 0 ? n : 1) * sizeof(int32_t));
+    oracle_blur_binomial(I, H, W, B);
+    oracle_laplace_i32(B, H, W, L);
+    long count = oracle_zero_crossings(L, H, W, t, edges);
+    if (L_out) memcpy(L_out, L, n * sizeof(int32_t));
+    free(B);
+    free(L);
+    return count;
+}
