@@ -14,8 +14,8 @@ the rate with one buffer set reused (cache-warm).
 
 Also reported (under "configs"): the integer pipeline at 4096^2 and on the
 16384^2 hysteresis stress image, the float pipeline at 7680x4320, the batched
-uneven-size plan against a per-image loop, and the differentiable front end
-forward + backward.  `roofline` describes the dominant kernel of the headline
+uneven-size plan against a per-image loop, the differentiable front end
+forward + backward, and the Laplacian zero-crossing detector at 4096^2.  `roofline` describes the dominant kernel of the headline
 step (the float walk: blur, Sobel, strength, suppression), timed with HIP
 events that the library records around it on the step's stream;
 `cpu_baseline` is the C oracle on the host.
@@ -185,6 +185,34 @@ def bench_u8(canny, torch, img, steps, warmup, label):
     del xs, es, ws
     torch.cuda.empty_cache()
     return out
+
+
+def bench_log(canny, torch, steps, warmup):
+    """Laplacian zero-crossing detector (binomial blur, 5-point Laplacian,
+    zero crossings with slope >= 10) on the 4096^2 uint8 scene: one kernel,
+    1 B/px in + 1 B/px out."""
+    import workloads
+    H = W = 4096
+    img = workloads.natural_u8(H, W, seed=10)
+    k = n_rot(H * W * 2)
+    xs = [torch.from_numpy(img).cuda() for _ in range(k)]
+    es = [torch.empty((H, W), dtype=torch.uint8, device="cuda") for _ in range(k)]
+    it = [0]
+
+    def step():
+        i = it[0] % k
+        it[0] += 1
+        canny.canny_log_u8(xs[i], 10, edges=es[i])
+
+    ms = timed(step, steps, warmup, torch.cuda.current_stream())
+    edge_frac = float((es[0] > 0).float().mean())
+    del xs, es
+    torch.cuda.empty_cache()
+    return {"workload": "Laplacian zero-crossing detector (5x5 binomial, 5-point Laplacian, "
+                        "slope threshold 10), 4096x4096 uint8",
+            "ms": round(ms, 4), "mpix_s": round(H * W / (ms * 1e-3) / 1e6, 1),
+            "hbm_frac": round(H * W * 2.0 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "edge_fraction": round(edge_frac, 4)}
 
 
 def bench_mag(canny, torch, steps, warmup):
@@ -413,8 +441,8 @@ def main():
         configs["u8_16384_spiral"] = bench_u8(canny, torch, workloads.spiral_u8(16384, seed=5),
                                               max(3, args.steps // 5), 2,
                                               "integer Canny, 16384x16384 spiral stress image")
-        for name, fn in (("batch_256_uneven", "bench_batch"), ("mag_fwd_bwd_32x1024", "bench_mag"),
-                         ("video_u8", "bench_video")):
+        for name, fn in (("log_u8_4096", "bench_log"), ("batch_256_uneven", "bench_batch"),
+                         ("mag_fwd_bwd_32x1024", "bench_mag"), ("video_u8", "bench_video")):
             f = globals().get(fn)
             if f is not None:
                 log(name)

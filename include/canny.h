@@ -177,6 +177,33 @@ int canny_f32_sector(const float* in, int64_t in_pitch, int H, int W, float sigm
                      float* mag_out, void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------
+ * Laplacian zero-crossing detector on uint8 images (the Laplace operator
+ * Laplace(f) = f_xx + f_yy that the paper's introduction names as the
+ * detector Canny is compared against), after the integer path's Step 1.
+ *
+ * B = the 5x5 binomial filter of canny_u8 (one rounding, replicate border);
+ * L = B(y,x-1) + B(y,x+1) + B(y-1,x) + B(y+1,x) - 4 B(y,x) (clamped reads);
+ * an edge pixel is
+ *   (a) the one nearer the zero (smaller |L|; the earlier pixel in raster
+ *       order on a tie) of two 4-neighbours inside the image whose L have
+ *       strictly opposite signs and |L(p) - L(q)| >= t, or
+ *   (b) a pixel with L = 0 whose left and right, or upper and lower,
+ *       neighbours (inside the image) have strictly opposite signs with a
+ *       difference >= t.
+ * One kernel; no workspace.
+ *
+ * in          uint8 H x W, pitch in_pitch bytes.
+ * t           slope threshold >= 0 (values above 2040 give no edges).
+ * edges       uint8 H x W output (255 / 0), pitch edges_pitch bytes.
+ * lap         optional int16 H x W output of L (pitch lap_pitch elements,
+ *             2-byte aligned) or NULL.
+ * Errors: NULL in or edges, H or W outside 1..2^20, a pitch < W, t < 0,
+ *         overlapping buffers -> CANNY_ERR_INVALID.
+ */
+int canny_log_u8(const uint8_t* in, int64_t in_pitch, int H, int W, int32_t t, uint8_t* edges,
+                 int64_t edges_pitch, int16_t* lap, int64_t lap_pitch, void* stream);
+
+/* ---------------------------------------------------------------------
  * Batched integer Canny over many images of uneven sizes.
  *
  * The same operator as canny_u8, applied to n independent images.  The

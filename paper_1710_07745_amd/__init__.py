@@ -20,7 +20,7 @@ from . import _lib
 from ._lib import CannyError, check, lib
 
 __all__ = [
-    "canny_u8", "canny_u8_noalloc", "canny_f32", "canny_f32_sector", "VideoStream", "hysteresis", "class_pitch", "u8_workspace_bytes", "f32_workspace_bytes",
+    "canny_u8", "canny_u8_noalloc", "canny_log_u8", "canny_f32", "canny_f32_sector", "VideoStream", "hysteresis", "class_pitch", "u8_workspace_bytes", "f32_workspace_bytes",
     "BatchPlan", "mag_forward", "mag_backward", "CannyMagnitude", "canny_magnitude",
     "CannyError", "StageTiming",
 ]
@@ -99,6 +99,24 @@ def canny_u8_noalloc(img: torch.Tensor, low: int = 40, high: int = 100, *, edges
                                 _ptr(class_map), _stream(img))
     check("canny_u8_noalloc", st)
     return edges
+
+
+def canny_log_u8(img: torch.Tensor, t: int = 10, *, edges: Optional[torch.Tensor] = None,
+                 return_laplacian: bool = False):
+    """Laplacian zero-crossing detector on a uint8 image: binomial blur,
+    5-point Laplacian L, edges at sign changes of L between 4-neighbours with
+    |L(p) - L(q)| >= t (on the pixel nearer the zero) and at zeros between
+    opposite neighbours.  Returns the edge map (255 / 0), and L (int16) if
+    ``return_laplacian``."""
+    _check_image(img, torch.uint8)
+    H, W = img.shape
+    if edges is None:
+        edges = torch.empty((H, W), dtype=torch.uint8, device=img.device)
+    lap = torch.empty((H, W), dtype=torch.int16, device=img.device) if return_laplacian else None
+    st = lib().canny_log_u8(img.data_ptr(), img.stride(0), H, W, int(t), edges.data_ptr(),
+                            edges.stride(0), _ptr(lap), W if lap is not None else 0, _stream(img))
+    check("canny_log_u8", st)
+    return (edges, lap) if return_laplacian else edges
 
 
 def hysteresis(class_map: torch.Tensor, H: int, W: int, *, edges: Optional[torch.Tensor] = None,

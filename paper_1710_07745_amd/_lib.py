@@ -34,6 +34,7 @@ SIGNATURES = {
     "canny_u8_workspace_bytes": (sz, [C.c_int, C.c_int]),
     "canny_u8": (C.c_int, [P, i64, C.c_int, C.c_int, i32, i32, P, i64, P, P, sz, P]),
     "canny_u8_noalloc": (C.c_int, [P, i64, C.c_int, C.c_int, i32, i32, P, i64, P, P]),
+    "canny_log_u8": (C.c_int, [P, i64, C.c_int, C.c_int, i32, P, i64, P, i64, P]),
     "canny_hysteresis_workspace_bytes": (sz, [C.c_int, C.c_int]),
     "canny_hysteresis": (C.c_int, [P, C.c_int, C.c_int, P, i64, P, sz, P]),
     "canny_f32_workspace_bytes": (sz, [C.c_int, C.c_int]),

@@ -28,6 +28,7 @@ UNROLL = ["-mllvm", "-pragma-unroll-threshold=1000000"]
 EXTRA = {
     "canny_f32_forward.hip": UNROLL + ["-fno-honor-nans"],
     "canny_u8_forward.hip": UNROLL,
+    "canny_log.hip": UNROLL,
 }
 EXTRA.update({f"canny_mag_g{g}.hip": UNROLL + ["-fno-honor-nans"] for g in range(1, 7)})
 

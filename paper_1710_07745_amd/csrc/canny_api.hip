@@ -313,6 +313,32 @@ int canny_f32_sector(const float* in, int64_t in_pitch, int H, int W, float sigm
                     mag_out, nullptr, ws, ws_bytes, stream, 1);
 }
 
+int canny_log_u8(const uint8_t* in, int64_t in_pitch, int H, int W, int32_t t, uint8_t* edges,
+                 int64_t edges_pitch, int16_t* lap, int64_t lap_pitch, void* stream) {
+    if (!in || !edges || !size_ok(H, W) || in_pitch < W || edges_pitch < W || t < 0)
+        return CANNY_ERR_INVALID;
+    if (lap && (lap_pitch < W || ((uintptr_t)lap % 2))) return CANNY_ERR_INVALID;
+    const size_t nin = image_bytes(H, in_pitch, W, 1), ne = image_bytes(H, edges_pitch, W, 1);
+    if (overlaps(in, nin, edges, ne)) return CANNY_ERR_INVALID;
+    if (lap) {
+        const size_t nl = image_bytes(H, lap_pitch, W, 2);
+        if (overlaps(in, nin, lap, nl) || overlaps(edges, ne, lap, nl)) return CANNY_ERR_INVALID;
+    }
+    if (!device_ok()) return CANNY_ERR_UNSUPPORTED;
+    LogArgs a;
+    a.in = in;
+    a.pitch = in_pitch;
+    a.H = H;
+    a.W = W;
+    a.t = t > 2041 ? 2041 : t;  // |L(p) - L(q)| <= 2040
+    a.edges = edges;
+    a.epitch = edges_pitch;
+    a.estore4 = ((uintptr_t)edges % 4 == 0) && (edges_pitch % 4 == 0);
+    a.lap = lap;
+    a.lpitch = lap_pitch;
+    return status_of(launch_log_u8(a, static_cast<hipStream_t>(stream)));
+}
+
 static bool mag_args_ok(const float* I, const float* sigma, int N, int H, int W, int radius) {
     return I && sigma && N >= 1 && size_ok(H, W) && radius >= 1 && radius <= 12 &&
            (int64_t)N * H * W <= ((int64_t)1 << 34);

@@ -121,6 +121,20 @@ struct F32FwdArgs {
     int skip_classify;  // signed path only: the hysteresis pass classifies instead
     int sector;         // one-launch path only: four-sector direction instead of interpolation
 };
+// Laplacian zero-crossing detector (canny_log.hip)
+struct LogArgs {
+    const uint8_t* in;
+    int64_t pitch;
+    int H, W;
+    int t;          // slope threshold, clamped to 0..2041 by the caller
+    uint8_t* edges;
+    int64_t epitch;
+    int estore4;    // edges 4-byte aligned with a pitch multiple of 4
+    int16_t* lap;   // optional Laplacian output or NULL
+    int64_t lpitch; // in elements
+};
+hipError_t launch_log_u8(const LogArgs& a, hipStream_t s);
+
 // stage timing (canny_timing.hip): timing_begin returns a slot (or -1 when
 // timing is off or the stage's pool is full) that timing_end closes
 int timing_begin(int stage, hipStream_t s);

@@ -92,6 +92,21 @@ def test_host_validation_u8_noalloc(lib):
     assert lib.canny_status_string(_lib.CANNY_ERR_TOO_LARGE).startswith(b"image too large")
 
 
+def test_host_validation_log(lib):
+    f = lib.canny_log_u8
+    E = C.c_void_p(0x900000)
+    assert f(None, 8, 8, 8, 10, E, 8, None, 0, None) == 1
+    assert f(FAKE, 8, 8, 8, 10, None, 8, None, 0, None) == 1
+    assert f(FAKE, 7, 8, 8, 10, E, 8, None, 0, None) == 1      # pitch < W
+    assert f(FAKE, 8, 8, 8, 10, E, 7, None, 0, None) == 1      # edges pitch < W
+    assert f(FAKE, 8, 8, 8, -1, E, 8, None, 0, None) == 1      # t < 0
+    assert f(FAKE, 8, 0, 8, 10, E, 8, None, 0, None) == 1
+    assert f(FAKE, 8, 8, 8, 10, C.c_void_p(0x1004), 8, None, 0, None) == 1  # aliases the input
+    assert f(FAKE, 8, 8, 8, 10, E, 8, C.c_void_p(0x800001), 8, None) == 1  # lap misaligned
+    assert f(FAKE, 8, 8, 8, 10, E, 8, C.c_void_p(0x800000), 7, None) == 1  # lap pitch < W
+    assert f(FAKE, 8, 8, 8, 10, E, 8, C.c_void_p(0x900004), 8, None) == 1  # lap aliases edges
+
+
 def test_host_validation_f32(lib):
     n = 1 << 40
     f = lib.canny_f32
