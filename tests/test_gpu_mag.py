@@ -2,14 +2,26 @@
 and its hand-written adjoint, against the fp64 oracle (which is itself pinned to
 finite differences and to torch autograd on the CPU).
 
-Tolerances: M within 2e-5 of max(M_64, 0.05 max M_64) per pixel (fp32 blur over
-2R+1 taps); dL/dI within 1e-4 in relative L2 norm and 1e-3 of max|dL/dI_64| per
-pixel (dM/dG = G/M loses relative accuracy where M is near 0, where fp32 G
-carries an absolute error of a few ulps of the image values); dL/dsigma within
-1e-4 relative.  The loss is the one of the differentiable workload: L = sum (M - T)^2
-with T the magnitude at sigma = 2."""
+Tolerances, derived from the arithmetic:
+- M within tol_fwd(R) of max(M_64, 0.05 max M_64) per pixel.  The float Canny
+  walk meets 1e-5 with 7 taps per blur pass; the worst-case rounding of an
+  n-term sum grows linearly with n, so the bound is 1e-5 * (2R+1) / 7 for
+  radii above 3 (2.7e-5 at the benchmark's R = 9) and 1e-5 up to R = 3.
+- dL/dI within 1e-4 of max|dL/dI_64| on every pixel outside the near-zero
+  set, and within 1e-4 in relative L2 norm.  dM/dG = G/M is not
+  differentiable at M = 0 and loses all relative accuracy near it (fp32 G
+  carries an absolute error of a few ulps of the image values), and that
+  error reaches dL/dI through the transposed Sobel and Gaussian stencils.  So
+  the near-zero set is every pixel within R + 1 (Chebyshev distance) of a
+  pixel whose oracle M is below 1e-4 of the image's largest; inside it the
+  bound is 1e-3 of max|dL/dI_64|.  Its size is printed and bounded (flat,
+  clipped regions of the scene have M = 0 exactly, so it is not empty).
+- dL/dsigma within 1e-4 relative.
+The loss is the one of the differentiable workload: L = sum (M - T)^2 with T
+the magnitude at sigma = 2."""
 import numpy as np
 import pytest
+import scipy.ndimage as ndi
 import torch
 
 import oracle
@@ -41,21 +53,32 @@ def gpu_fwd_bwd(canny, I, sig, R, T=None):
     return M.cpu().numpy(), gM.cpu().numpy(), dI.cpu().numpy(), ds.cpu().numpy()
 
 
-def check_image(I, sig, R, M, gM, dI, ds, mtol=2e-5):
+def tol_fwd(R):
+    return 1e-5 * max(1.0, (2 * R + 1) / 7.0)
+
+
+def check_image(I, sig, R, M, gM, dI, ds, label="", max_near=0.25):
     oM = oracle.mag_forward(I.astype(np.float64), float(sig), R)
     err = np.abs(M - oM) / np.maximum(oM, 0.05 * oM.max() + 1e-30)
-    assert err.max() <= mtol, f"M error {err.max():.3g}"
     odI, ods = oracle.mag_backward(I.astype(np.float64), float(sig), gM.astype(np.float64), R)
     scale = np.abs(odI).max() + 1e-30
+    e = np.abs(dI - odI) / scale
     l2 = np.linalg.norm(dI - odI) / (np.linalg.norm(odI) + 1e-30)
-    worst = np.unravel_index(np.argmax(np.abs(dI - odI)), dI.shape)
-    info = (f"dI max err {np.abs(dI - odI).max() / scale:.3g} of max, L2 {l2:.3g}, worst at {worst} "
-            f"M there {oM[worst]:.3g} (max M {oM.max():.3g}), min M nearby "
-            f"{oM[max(0, worst[0] - 3):worst[0] + 4, max(0, worst[1] - 3):worst[1] + 4].min():.3g}; "
-            f"dsigma {ds} vs {ods}")
-    print(info)
+    zero = oM < 1e-4 * oM.max()
+    near = ndi.binary_dilation(zero, structure=np.ones((2 * R + 3, 2 * R + 3), bool)) if zero.any() else zero
+    far_err = e[~near].max() if (~near).any() else 0.0
+    near_err = e[near].max() if near.any() else 0.0
+    info = (f"[mag {label} {I.shape[0]}x{I.shape[1]} R={R} sigma={float(sig):.3f}] M error {err.max():.3g} "
+            f"(bound {tol_fwd(R):.3g}); dI error {far_err:.3g} of max off the near-zero set, "
+            f"{near_err:.3g} on it ({near.mean():.3f} of the pixels, M < 1e-4 max on {zero.mean():.4f}); "
+            f"L2 {l2:.3g}; dsigma {float(ds):.6g} vs {ods:.6g}")
+    print(info, flush=True)
+    assert err.max() <= tol_fwd(R), info
+    assert far_err <= 1e-4, info
+    assert near_err <= 1e-3, info
+    if max_near is not None:  # tiny images can lie wholly inside the set
+        assert near.mean() <= max_near, info
     assert l2 <= 1e-4, info
-    assert np.abs(dI - odI).max() <= 1e-3 * scale, info
     assert abs(ds - ods) <= 1e-4 * abs(ods) + 1e-6, info
 
 
@@ -66,7 +89,7 @@ def test_mag_radii(canny, R):
     sig = np.linspace(0.6 + 0.2 * R, 0.9 + 0.25 * R, N).astype(np.float32)
     M, gM, dI, ds = gpu_fwd_bwd(canny, I, sig, R)
     for n in range(N):
-        check_image(I[n], sig[n], R, M[n], gM[n], dI[n], ds[n])
+        check_image(I[n], sig[n], R, M[n], gM[n], dI[n], ds[n], label="radius")
 
 
 @pytest.mark.parametrize("H,W", [(1, 1), (1, 7), (6, 1), (2, 3), (5, 5), (17, 300), (300, 17),
@@ -76,7 +99,7 @@ def test_mag_sizes(canny, H, W):
     sig = np.array([1.3, 2.7], np.float32)
     M, gM, dI, ds = gpu_fwd_bwd(canny, I, sig, 9)
     for n in range(2):
-        check_image(I[n], sig[n], 9, M[n], gM[n], dI[n], ds[n])
+        check_image(I[n], sig[n], 9, M[n], gM[n], dI[n], ds[n], label="size", max_near=None)
 
 
 def test_mag_config_1024(canny):
@@ -87,7 +110,7 @@ def test_mag_config_1024(canny):
     sig = workloads.sigma_init(N, seed=4)
     M, gM, dI, ds = gpu_fwd_bwd(canny, I, sig, 9)
     for n in (0, 7, 19, 31):
-        check_image(I[n], sig[n], 9, M[n], gM[n], dI[n], ds[n])
+        check_image(I[n], sig[n], 9, M[n], gM[n], dI[n], ds[n], label=f"32x1024^2 image {n}")
 
 
 def test_mag_finite_difference_64(canny):
