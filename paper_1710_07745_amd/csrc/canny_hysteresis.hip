@@ -17,11 +17,11 @@
 //              read-only walk.  A component that does not touch the tile
 //              border is decided here: its pixels get 255 if it holds a
 //              strong pixel, else 0.  A component that touches the border is
-//              named globally by tile * 64T + its root; the pass writes, per
-//              tile-border pixel, that name (or -1), initialises parent/flag
-//              for it (sparse arrays indexed by name), and gives its pixels
-//              the pending code 1 + b, b (0..251) the index of one of the
-//              component's border pixels.  Non-candidates get 0.
+//              named globally by tile * 256 + b, b (0..251) the largest index
+//              of its border pixels; the pass writes, per tile-border pixel,
+//              that name (or -1), initialises parent/flag for it (dense arrays
+//              of 256 entries per tile, indexed by name), and gives its pixels
+//              the pending code 1 + b.  Non-candidates get 0.
 //   2. merge:  one thread per tile-border pixel on the right and bottom tile
 //              edges unions its component with the 8-connected candidates
 //              across the edge (global union-find, atomicMin linking).
@@ -282,6 +282,8 @@ __device__ __forceinline__ void for_slots(int r, int c, int th, int tw, F f) {
 constexpr int kRootMask = 0xFFFF;
 constexpr int kStrongBit = 1 << 16;
 constexpr int kBrepShift = 17;
+// global names of border components: tile * kNamesPerTile + border index
+constexpr int kNamesPerTile = 256;
 
 template <int T>
 struct LocalSmem {
@@ -355,34 +357,41 @@ __device__ __forceinline__ void local_tile(const HystArgs& a, int tile, int tile
         atomicOr(&L[L[me + run_start(st.S, c)] & kRootMask], kStrongBit);
     }
     __syncthreads();
-    // border pixels: name the component globally and point it at a border index
-    const bool edge_row = r == 0 || r == g.th - 1;
-    if (edge_row || cb == 0 || cb + TL::kPPT >= g.tw) {
-        const int64_t gbase = (int64_t)g.tile * TL::kPx;
+    // border pixels point their component at its largest border index
+    const bool border_seg = r == 0 || r == g.th - 1 || cb == 0 || cb + TL::kPPT >= g.tw;
+    if (border_seg) {
         for (uint32_t b = st.cand; b; b &= b - 1) {
             const int c = cb + __ffs(b) - 1;
             const int bi = border_index(r, c, g.th, g.tw);
             if (bi < 0) continue;
             const int root = L[me + run_start(st.S, c)] & kRootMask;
             const int low = root | (L[root] & kStrongBit);  // final: no strong marks remain
-            const int64_t gid = gbase + root;
-            // every border pixel of the component stores the same values
-            a.parent[gid] = (int)gid;
-            a.flag[gid] = low >> 16;
             atomicMax(&L[root], low | ((1 + bi) << kBrepShift));  // the largest index wins
-            for_slots<T>(r, c, g.th, g.tw, [&](int s) { bl[s] = (int)gid; });
         }
     }
     __syncthreads();
     bool pending = false;
     if (r < g.th) {
         Seg16 out;
+        const int nbase = g.tile * kNamesPerTile;
         for (uint32_t b = st.cand; b; b &= b - 1) {
             const int k = __ffs(b) - 1;
             const int v = L[L[me + run_start(st.S, cb + k)] & kRootMask];
             const uint32_t br = (uint32_t)v >> kBrepShift;
             pending |= br != 0;
             out.set(k, br ? br : ((v & kStrongBit) ? 255u : 0u));
+            if (border_seg && br) {
+                // the component's global name, in this pixel's border slots;
+                // the representative pixel itself starts the union-find entry
+                const int bi = border_index(r, cb + k, g.th, g.tw);
+                if (bi < 0) continue;
+                const int name = nbase + (int)br - 1;
+                for_slots<T>(r, cb + k, g.th, g.tw, [&](int s) { bl[s] = name; });
+                if (bi == (int)br - 1) {
+                    a.parent[name] = name;
+                    a.flag[name] = (v & kStrongBit) ? 1 : 0;
+                }
+            }
         }
         const int valid = min(a.W - (g.X0 + cb), TL::kPPT);
         if (valid > 0) store_seg(a.edges + (int64_t)(g.Y0 + r) * a.epitch + g.X0 + cb, out, valid, vec16);
@@ -390,6 +399,7 @@ __device__ __forceinline__ void local_tile(const HystArgs& a, int tile, int tile
     // one bit per thread segment with pending codes, one word per wave
     const uint64_t pm = __ballot(pending);
     if ((t & (kWave - 1)) == 0) a.pmask[(int64_t)g.tile * (kWGThreads / kWave) + t / kWave] = pm;
+    __syncthreads();  // every border slot's name is in bl
     const int base = g.tile * TL::kPerim;
     for (int s = t; s < TL::kPerim; s += kWGThreads) a.blab[base + s] = bl[s];
 }
@@ -625,26 +635,26 @@ static int perim(int tile_rows) { return 2 * kHystCols + 2 * tile_rows; }
 
 static size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-// blab: int32 per border slot; parent, flag: int32 per tile pixel (sparsely
-// touched: only entries named by a border component); pmask: one 64-bit word
-// per wave of a tile
+// blab: int32 per border slot; parent, flag: int32 per component name (256
+// per tile; only the names of this call's border components are written and
+// read); pmask: one 64-bit word per wave of a tile.  About 0.76 B per pixel.
 size_t hyst_workspace_bytes(int H, int W, int tile_rows) {
     const size_t ntiles = (size_t)ceil_div(W, kHystCols) * ceil_div(H, tile_rows);
-    const size_t npx = ntiles * (size_t)kHystCols * tile_rows;
-    return al256(ntiles * perim(tile_rows) * 4) + 2 * al256(npx * 4) +
+    const size_t nnames = ntiles * (size_t)kNamesPerTile;
+    return al256(ntiles * perim(tile_rows) * 4) + 2 * al256(nnames * 4) +
            al256(ntiles * (kWGThreads / kWave) * 8);
 }
 
 void hyst_carve(void* ws, int H, int W, int tile_rows, HystArgs& a) {
     const size_t ntiles = (size_t)ceil_div(W, kHystCols) * ceil_div(H, tile_rows);
-    const size_t npx = ntiles * (size_t)kHystCols * tile_rows;
+    const size_t nnames = ntiles * (size_t)kNamesPerTile;
     char* p = static_cast<char*>(ws);
     a.blab = reinterpret_cast<int32_t*>(p);
     p += al256(ntiles * perim(tile_rows) * 4);
     a.parent = reinterpret_cast<int32_t*>(p);
-    p += al256(npx * 4);
+    p += al256(nnames * 4);
     a.flag = reinterpret_cast<int32_t*>(p);
-    p += al256(npx * 4);
+    p += al256(nnames * 4);
     a.pmask = reinterpret_cast<uint64_t*>(p);
 }
 
