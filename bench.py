@@ -373,6 +373,64 @@ def cpu_paper_design(reps=3):
             "speedup_asymmetric_sqrt_perf": asym}
 
 
+def profile_workload(canny, torch, what, steps):
+    """A few calls of one workload on one buffer set, then a 256 MiB device
+    copy (the calibration kernel of the traffic counters).  Each workload runs
+    alone so that per-kernel counter medians never mix workloads."""
+    import numpy as np
+    import workloads
+    dev = "cuda"
+    if what == "f32_4096":
+        X = torch.from_numpy(workloads.natural_u8(4096, 4096, seed=1).astype(np.float32)).to(dev)
+        E = torch.empty((4096, 4096), dtype=torch.uint8, device=dev)
+        ws = torch.empty(canny.f32_workspace_bytes(4096, 4096), dtype=torch.uint8, device=dev)
+        for _ in range(steps):
+            canny.canny_f32(X, 1.4, 3, 0.05, 0.15, True, edges=E, workspace=ws)
+    elif what in ("u8_4096", "u8_16384_spiral"):
+        img = (workloads.natural_u8(4096, 4096, seed=10) if what == "u8_4096"
+               else workloads.spiral_u8(16384, seed=5))
+        X = torch.from_numpy(img).to(dev)
+        E = torch.empty_like(X)
+        ws = torch.empty(canny.u8_workspace_bytes(*img.shape), dtype=torch.uint8, device=dev)
+        for _ in range(steps):
+            canny.canny_u8(X, 40, 100, edges=E, workspace=ws)
+    elif what == "log_4096":
+        X = torch.from_numpy(workloads.natural_u8(4096, 4096, seed=10)).to(dev)
+        E = torch.empty_like(X)
+        for _ in range(steps):
+            canny.canny_log_u8(X, 10, edges=E)
+    elif what == "mag_32x1024":
+        N, H, W, R = 32, 1024, 1024, 9
+        I = torch.from_numpy(np.stack([workloads.natural_unit_f32(H, W, seed=2000 + i)
+                                       for i in range(N)])).to(dev)
+        sig = torch.from_numpy(workloads.sigma_init(N, seed=4)).to(dev)
+        gM = torch.ones_like(I)
+        for _ in range(steps):
+            canny.mag_forward(I, sig, R)
+            canny.mag_backward(I, sig, gM, R)
+    elif what == "batch_256":
+        shapes = workloads.batch_shapes(256, seed=3)
+        xs = [torch.from_numpy(workloads.natural_u8(h, w, seed=1000 + i)).to(dev)
+              for i, (h, w) in enumerate(shapes)]
+        outs = [torch.empty((h, w), dtype=torch.uint8, device=dev) for h, w in shapes]
+        plan = canny.BatchPlan(shapes, 40, 100, autotune=False)
+        ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
+        for _ in range(steps):
+            plan.run(xs, outs, ws)
+        torch.cuda.synchronize()
+        plan.close()
+    src = torch.empty(256 << 20, dtype=torch.uint8, device=dev).fill_(1)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(steps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile": what, "steps": steps, "copy_bytes": 256 << 20}), flush=True)
+
+
+PROFILE_WORKLOADS = ("f32_4096", "u8_4096", "u8_16384_spiral", "log_4096", "mag_32x1024", "batch_256")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -383,6 +441,9 @@ def main():
     ap.add_argument("--profile-roofline", action="store_true",
                     help="only the headline step (float Canny, 4096^2, one buffer set) and a "
                          "256 MiB device copy, for hardware-counter runs")
+    ap.add_argument("--profile", choices=sorted(PROFILE_WORKLOADS),
+                    help="only --steps runs of one workload (one buffer set) and a 256 MiB "
+                         "device copy, for per-kernel counter runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -392,6 +453,10 @@ def main():
     import torch
     import paper_1710_07745_amd as canny
     torch.cuda.set_device(0)
+
+    if args.profile:
+        profile_workload(canny, torch, args.profile, args.steps)
+        return
 
     if args.profile_roofline:
         import numpy as np

@@ -327,13 +327,63 @@ struct Seg16 {
     }
 };
 
+// A full 16-byte segment at any alignment: one 16-byte store when aligned;
+// otherwise the bytes before the first 4-byte boundary, three aligned dwords
+// and the bytes after them (every byte written lies inside the segment, so
+// neighbouring segments of other threads are never touched).  Rows whose
+// pitch is not a multiple of 16 (uneven widths) take this path.
 __device__ __forceinline__ void store_seg(uint8_t* dst, const Seg16& o, int valid, int vec16) {
+    const uint32_t w[4] = {(uint32_t)o.lo, (uint32_t)(o.lo >> 32), (uint32_t)o.hi, (uint32_t)(o.hi >> 32)};
     if (vec16 && valid == 16) {
-        *reinterpret_cast<uint4*>(dst) = make_uint4((uint32_t)o.lo, (uint32_t)(o.lo >> 32),
-                                                     (uint32_t)o.hi, (uint32_t)(o.hi >> 32));
+        *reinterpret_cast<uint4*>(dst) = make_uint4(w[0], w[1], w[2], w[3]);
+    } else if (valid == 16) {
+        const int k = (int)((uintptr_t)dst & 3);
+        if (k == 0) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) reinterpret_cast<uint32_t*>(dst)[i] = w[i];
+        } else {
+            const int h = 4 - k;  // bytes up to the first 4-byte boundary
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+                if (b < h) dst[b] = (uint8_t)(w[0] >> (8 * b));
+            uint32_t* d32 = reinterpret_cast<uint32_t*>(dst + h);
+#pragma unroll
+            for (int i = 0; i < 3; ++i) d32[i] = __builtin_amdgcn_alignbyte(w[i + 1], w[i], h);
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+                if (b < k) dst[16 - k + b] = (uint8_t)(w[3] >> (8 * (h + b)));
+        }
     } else {
         for (int k = 0; k < valid; ++k) dst[k] = (uint8_t)o.get(k);
     }
+}
+
+// A full segment read at any alignment.  Unaligned: the aligned dwords that
+// cover it (up to 3 bytes either side), joined by byte funnel shifts; used
+// only where those extra bytes lie inside the row (wide_ok: at least 4
+// columns before the segment and 4 after it).
+__device__ __forceinline__ Seg16 load_seg(const uint8_t* src, int valid, int vec16, bool wide_ok) {
+    Seg16 out;
+    if (vec16 && valid == 16) {
+        const uint4 v = *reinterpret_cast<const uint4*>(src);
+        out.lo = v.x | (uint64_t)v.y << 32;
+        out.hi = v.z | (uint64_t)v.w << 32;
+    } else if (valid == 16 && (((uintptr_t)src & 3) == 0 || wide_ok)) {
+        const int k = (int)((uintptr_t)src & 3);
+        const uint32_t* s32 = reinterpret_cast<const uint32_t*>(src - k);
+        uint32_t d[5];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) d[i] = s32[i];
+        d[4] = k ? s32[4] : 0u;
+        uint32_t w[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) w[i] = __builtin_amdgcn_alignbyte(d[i + 1], d[i], k);
+        out.lo = w[0] | (uint64_t)w[1] << 32;
+        out.hi = w[2] | (uint64_t)w[3] << 32;
+    } else {
+        for (int k = 0; k < valid; ++k) out.set(k, src[k]);
+    }
+    return out;
 }
 
 // Pass 1 on one tile (the whole workgroup takes part).
@@ -407,7 +457,9 @@ __device__ __forceinline__ void local_tile(const HystArgs& a, int tile, int tile
 template <int T>
 __global__ void __launch_bounds__(kWGThreads) k_hyst_local(HystArgs a, int tiles_x, int vec16) {
     __shared__ LocalSmem<T> sm;
-    local_tile<T>(a, blockIdx.x, tiles_x, vec16, sm);
+    // each XCD takes a contiguous range of tiles: neighbouring tiles share the
+    // cache lines of the class map and the edge map, and each XCD has its own L2
+    local_tile<T>(a, xcd_remap(blockIdx.x, gridDim.x), tiles_x, vec16, sm);
 }
 
 // Pass 2 for border pixel k of a tile (k < T: right edge row k; else bottom
@@ -448,7 +500,7 @@ template <int T>
 __global__ void __launch_bounds__(kWGThreads)
 k_hyst_merge(HystArgs a, int tiles_x, int tiles_y, int ntiles) {
     const int per_tile = T + kHystCols;
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t gid = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (gid >= (int64_t)ntiles * per_tile) return;
     const int tile = (int)(gid / per_tile);
     merge_one<T>(a, tile, (int)(gid - (int64_t)tile * per_tile), tiles_x, tiles_y);
@@ -473,7 +525,7 @@ __device__ __forceinline__ void flags_one(const HystArgs& a, int s) {
 }
 
 __global__ void __launch_bounds__(kWGThreads) k_hyst_flags(HystArgs a, int nslots) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    const int s = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (s < nslots) flags_one(a, s);
 }
 
@@ -505,13 +557,8 @@ __device__ __forceinline__ void resolve_tile(const HystArgs& a, int tile, int ti
     // lookups below
     Seg16 out;
     if (mine) {
-        if (vec16 && valid == TL::kPPT) {
-            const uint4 v = *reinterpret_cast<const uint4*>(dst);
-            out.lo = v.x | (uint64_t)v.y << 32;
-            out.hi = v.z | (uint64_t)v.w << 32;
-        } else {
-            for (int k = 0; k < valid; ++k) out.set(k, dst[k]);
-        }
+        const int col0 = g.X0 + cb;
+        out = load_seg(dst, valid, vec16, col0 >= 4 && col0 + TL::kPPT + 4 <= a.W);
     }
     const int base = g.tile * TL::kPerim;
     if (t < 2 * kHystCols + 2 * (T - 2)) {
@@ -532,7 +579,7 @@ __device__ __forceinline__ void resolve_tile(const HystArgs& a, int tile, int ti
 template <int T>
 __global__ void __launch_bounds__(kWGThreads) k_hyst_resolve(HystArgs a, int tiles_x, int vec16) {
     __shared__ uint8_t res[kWGThreads];
-    resolve_tile<T>(a, blockIdx.x, tiles_x, vec16, res);
+    resolve_tile<T>(a, xcd_remap(blockIdx.x, gridDim.x), tiles_x, vec16, res);
 }
 
 template <int T>
@@ -576,7 +623,7 @@ template <int T>
 __global__ void __launch_bounds__(kWGThreads)
 k_hyst_local_batch(const BatchImage* imgs, const BatchDev* hdr) {
     __shared__ LocalSmem<T> sm;
-    const int task = blockIdx.x;
+    const int task = xcd_remap(blockIdx.x, gridDim.x);
     if (task >= hdr->total_tiles) return;
     const BatchImage& im = imgs[hdr->tile_img[task]];
     const int vec16 = ((uintptr_t)im.edges % 16 == 0) && (im.epitch % 16 == 0);
@@ -585,7 +632,7 @@ k_hyst_local_batch(const BatchImage* imgs, const BatchDev* hdr) {
 
 template <int T>
 __global__ void __launch_bounds__(kWGThreads) k_hyst_merge_batch(const BatchImage* imgs, const BatchDev* hdr) {
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int g = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (g >= hdr->total_merge) return;
     const BatchImage& im = imgs[hdr->tile_img[g / (T + kHystCols)]];
     const int local = g - im.merge_base;
@@ -594,7 +641,7 @@ __global__ void __launch_bounds__(kWGThreads) k_hyst_merge_batch(const BatchImag
 }
 
 __global__ void __launch_bounds__(kWGThreads) k_hyst_flags_batch(const BatchImage* imgs, const BatchDev* hdr) {
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int g = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (g >= hdr->total_slots) return;
     const BatchImage& im = imgs[hdr->tile_img[g / Tile<64>::kPerim]];
     flags_one(batch_args(im, hdr->ws), g - im.slot_base);
@@ -606,7 +653,7 @@ k_hyst_resolve_batch(const BatchImage* imgs, const BatchDev* hdr) {
     // one workgroup per tile of the batch (most tiles exit at once, so the
     // hardware dispatcher, not a software loop, should pace them)
     __shared__ uint8_t res[kWGThreads];
-    const int task = blockIdx.x;
+    const int task = xcd_remap(blockIdx.x, gridDim.x);
     if (task >= hdr->total_tiles) return;
     const BatchImage& im = imgs[hdr->tile_img[task]];
     const int vec16 = ((uintptr_t)im.edges % 16 == 0) && (im.epitch % 16 == 0);

@@ -6,6 +6,10 @@
   python -m paper_1710_07745_amd.profiling valu PMC_DIR [--kernel SUBSTR] [--command C ...]
       VALU instructions (SQ_INSTS_VALU, per wave) and waves (SQ_WAVES) per
       launch of the kernel, from one counter run (median over dispatches).
+  python -m paper_1710_07745_amd.profiling traffic-table FETCH_DIR WRITE_DIR
+      --copy-bytes N --kernel NAME=ALG_BYTES [--kernel ...]
+      the same for several kernels of one run pair, as a table with each
+      kernel's algorithmic bytes and the ratio.
   python -m paper_1710_07745_amd.profiling counters PMC_DIR --kernel SUBSTR [--kernel ...]
       every counter of one run, median per dispatch, for each kernel named.
   python -m paper_1710_07745_amd.profiling traffic FETCH_DIR WRITE_DIR
@@ -95,7 +99,7 @@ def stats(args) -> None:
               f"{float(r['MaxNs']) / 1e3:9.2f} {float(r['Percentage']):7.2f}  {short(r['Name'])}")
 
 
-def _per_dispatch(d: str, counter: str, substr: str):
+def _per_dispatch(d: str, counter: str, substr: str, pick: str = "median"):
     vals = []
     for r in csv.DictReader(open(_one(os.path.join(d, "*counter_collection.csv")))):
         if r["Counter_Name"] == counter and substr in r["Kernel_Name"]:
@@ -103,15 +107,17 @@ def _per_dispatch(d: str, counter: str, substr: str):
     if not vals:
         sys.exit(f"no {counter} rows for kernels matching {substr!r} in {d}")
     vals.sort()
-    return vals[len(vals) // 2], len(vals)  # median: ignores a stray upload copy
+    if pick == "max":  # the calibration copy: the largest copy of the run, not an upload
+        return vals[-1], len(vals)
+    return vals[len(vals) // 2], len(vals)
 
 
 def traffic(args) -> None:
     kib = 1024.0
     f_k, nf = _per_dispatch(args.fetch_dir, "FETCH_SIZE", args.kernel)
     w_k, nw = _per_dispatch(args.write_dir, "WRITE_SIZE", args.kernel)
-    f_c, _ = _per_dispatch(args.fetch_dir, "FETCH_SIZE", COPY_KERNEL)
-    w_c, _ = _per_dispatch(args.write_dir, "WRITE_SIZE", COPY_KERNEL)
+    f_c, _ = _per_dispatch(args.fetch_dir, "FETCH_SIZE", COPY_KERNEL, "max")
+    w_c, _ = _per_dispatch(args.write_dir, "WRITE_SIZE", COPY_KERNEL, "max")
     fs = args.copy_bytes / (f_c * kib)
     ws = args.copy_bytes / (w_c * kib)
     total = f_k * kib * fs + w_k * kib * ws
@@ -133,6 +139,31 @@ def traffic(args) -> None:
     if args.alg_bytes:
         print(f"algorithmic_bytes_per_launch: {args.alg_bytes:.0f}")
         print(f"traffic_over_algorithmic: {total / args.alg_bytes:.3f}")
+
+
+def traffic_table(args) -> None:
+    """HBM bytes per launch of several kernels of one run pair, each counter
+    scaled by its reading for the copy kernel, beside the kernel's algorithmic
+    bytes (NAME=BYTES; 0 when the kernel has no figure of its own)."""
+    kib = 1024.0
+    f_c, _ = _per_dispatch(args.fetch_dir, "FETCH_SIZE", COPY_KERNEL, "max")
+    w_c, _ = _per_dispatch(args.write_dir, "WRITE_SIZE", COPY_KERNEL, "max")
+    fs = args.copy_bytes / (f_c * kib)
+    ws = args.copy_bytes / (w_c * kib)
+    print(f"# HBM traffic per launch (FETCH_SIZE x {fs:.4f}, WRITE_SIZE x {ws:.4f}: the factors "
+          f"that make a {args.copy_bytes:.0f}-byte device copy read and write its size)")
+    for c in args.command or []:
+        print(f"# command: {c}")
+    print(f"{'kernel':48s} {'fetch_MB':>10s} {'write_MB':>10s} {'total_MB':>10s} {'alg_MB':>10s} {'ratio':>7s}")
+    for spec in args.kernel:
+        name, _, alg = spec.rpartition("=")
+        alg = float(alg)
+        f_k, _ = _per_dispatch(args.fetch_dir, "FETCH_SIZE", name)
+        w_k, _ = _per_dispatch(args.write_dir, "WRITE_SIZE", name)
+        fb, wb = f_k * kib * fs, w_k * kib * ws
+        ratio = f"{(fb + wb) / alg:7.2f}" if alg > 0 else f"{'-':>7s}"
+        alg_s = f"{alg / 1e6:10.1f}" if alg > 0 else f"{'-':>10s}"
+        print(f"{name[:48]:48s} {fb / 1e6:10.1f} {wb / 1e6:10.1f} {(fb + wb) / 1e6:10.1f} {alg_s} {ratio}")
 
 
 def valu(args) -> None:
@@ -179,6 +210,12 @@ def main(argv=None) -> None:
     t.add_argument("--copy-bytes", type=float, required=True)
     t.add_argument("--alg-bytes", type=float, default=0.0)
     t.add_argument("--command", action="append")
+    tt = sub.add_parser("traffic-table")
+    tt.add_argument("fetch_dir")
+    tt.add_argument("write_dir")
+    tt.add_argument("--kernel", action="append", required=True, help="NAME=ALG_BYTES")
+    tt.add_argument("--copy-bytes", type=float, required=True)
+    tt.add_argument("--command", action="append")
     v = sub.add_parser("valu")
     v.add_argument("dir")
     v.add_argument("--kernel", default=WALK_KERNEL)
@@ -188,7 +225,8 @@ def main(argv=None) -> None:
     c.add_argument("--kernel", action="append", required=True)
     c.add_argument("--command", action="append")
     a = ap.parse_args(argv)
-    {"stats": stats, "traffic": traffic, "valu": valu, "counters": counters}[a.cmd](a)
+    {"stats": stats, "traffic": traffic, "traffic-table": traffic_table, "valu": valu,
+     "counters": counters}[a.cmd](a)
 
 
 if __name__ == "__main__":

@@ -228,3 +228,21 @@ def test_spiral_stress_16384(canny, noise):
           f"{time.time() - t0:.1f} s", flush=True)
     if noise == 0.0:
         assert depth > 1000000 and nstrong == 1
+
+
+@pytest.mark.parametrize("off", [1, 2, 3, 5])
+def test_edges_into_misaligned_rows(canny, off):
+    """Edge rows that start at every alignment (a row view at a byte offset
+    into a buffer with an odd pitch): the hysteresis writes and rereads
+    16-pixel segments at any alignment, touching no byte outside the image
+    (guard bytes 0xA5 around every row stay as they were)."""
+    H, W = 203, 1001
+    img = workloads.natural_u8(H, W, seed=70 + off)
+    big = torch.full((H, W + 9), 0xA5, dtype=torch.uint8, device="cuda")
+    view = big[:, off:off + W]
+    canny.canny_u8(torch.from_numpy(img).cuda(), 40, 100, edges=view)
+    torch.cuda.synchronize()
+    oe, _ = oracle.canny_u8(img, 40, 100)
+    b = big.cpu().numpy()
+    assert np.array_equal(b[:, off:off + W], oe)
+    assert (b[:, :off] == 0xA5).all() and (b[:, off + W:] == 0xA5).all()
