@@ -292,23 +292,37 @@ def bench_video(canny, torch, steps, warmup):
         frames = [torch.from_numpy(workloads.natural_u8(H, W, seed=900 + i)).pin_memory()
                   for i in range(4)]
         outs = [torch.empty((H, W), dtype=torch.uint8).pin_memory() for _ in range(4)]
-        res = {}
+        res, push_us = {}, {}
         for depth in (3, 1):
             vs = canny.VideoStream(H, W, 40, 100, depth=depth)
             for i in range(4):
                 vs.push(frames[i], outs[i])
             vs.sync()
             t0 = time.perf_counter()
+            t_push = 0.0
             for i in range(n):
+                tp = time.perf_counter()
                 vs.push(frames[i % 4], outs[i % 4])
+                t_push += time.perf_counter() - tp
             vs.sync()
             dt = time.perf_counter() - t0
             vs.close()
             res[depth] = n / dt
+            push_us[depth] = t_push / n * 1e6
+        # the link alone: one frame up and one down per step, each direction
+        # timed on its own (pinned buffers), the slower sets the streaming bound
+        d = torch.empty((H, W), dtype=torch.uint8, device="cuda")
+        st = torch.cuda.current_stream()
+        up = timed(lambda: d.copy_(frames[0], non_blocking=True), 10, 2, st)
+        down = timed(lambda: outs[0].copy_(d, non_blocking=True), 10, 2, st)
+        del d
         out[label] = {"frames": n, "shape": [H, W], "fps": round(res[3], 1),
                       "mpix_s": round(res[3] * H * W / 1e6, 1),
                       "fps_serialized": round(res[1], 1),
-                      "overlap_speedup": round(res[3] / res[1], 3)}
+                      "overlap_speedup": round(res[3] / res[1], 3),
+                      "host_push_us_per_frame": round(push_us[3], 1),
+                      "h2d_ms": round(up, 4), "d2h_ms": round(down, 4),
+                      "fps_link_bound": round(1e3 / max(up, down), 1)}
         del frames, outs
     out["workload"] = ("streaming integer Canny from pinned host frames to host edge maps "
                        "(PCIe-inclusive), 3-slot ring vs 1 slot")

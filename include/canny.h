@@ -241,13 +241,14 @@ void canny_batch_plan_destroy(canny_batch_plan* plan);
  * Streaming integer Canny over a sequence of host frames of one size (the
  * operator of canny_u8, Steps 1-4, per frame).
  *
- * The stream owns `depth` device slots (frame, edge map, workspace) and
- * three HIP streams (upload, detect, download; default priority).  A push
- * enqueues, for the next slot in ring order: the host-to-device copy of
- * the frame, canny_u8 on it after that copy, and the device-to-host copy of
- * the edge map after the detection; a slot is reused only after its
- * previous download has completed.  All ordering is by device events, so
- * with depth >= 3 copies in both directions overlap the detection.
+ * The stream owns `depth` device slots (frame, edge map, workspace), each
+ * with its own HIP stream (default priority).  A push enqueues, on the next
+ * slot's stream in ring order: the host-to-device copy of the frame,
+ * canny_u8 on it, and the device-to-host copy of the edge map.  The slot's
+ * stream orders its reuse after its previous frame; the slots' streams run
+ * concurrently, so with depth >= 3 copies in both directions overlap the
+ * detection.  Frames may complete out of order; canny_video_sync waits for
+ * all of them.
  *
  * canny_video_create: H, W as canny_u8 accepts them (1 <= H, W <= 2^20 and
  *   ceil(H/64) * ceil(W/64) * 4096 < 2^31), 0 <= low <= high,

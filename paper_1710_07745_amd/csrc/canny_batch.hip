@@ -15,13 +15,16 @@
 // buffers never need a new recording.
 //
 // Tuning: the forward's tile height (output rows per wave) is picked by
-// timing every candidate on the plan's own sizes with synthetic content, when
-// asked; results are kept per process and, if CANNY_TUNE_CACHE names a file,
-// in that file as "key rows" lines (key: arch, CU count, image count, hash of
-// the sizes).
+// timing the candidates on the plan's own sizes with synthetic content, when
+// asked, within a time budget; results are kept per process and, if
+// CANNY_TUNE_CACHE names a file, in that file as "key rows" lines.  The key
+// is a size bucket (arch, CU count, and the image count, total pixels, mean
+// height and mean width, each on a logarithmic grid), so batches of a
+// similar make-up share one entry instead of re-tuning per exact size list.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -53,10 +56,14 @@ struct canny_batch_plan {
     BatchImage* d_imgs = nullptr;
     BatchDev* d_hdr = nullptr;
     int32_t* d_tile_img = nullptr;  // per tile: index of its image (fixed by the sizes)
-    BatchImage* h_stage = nullptr;  // pinned staging of the descriptor table
-    BatchDev* h_stage_hdr = nullptr;
-    hipEvent_t uploaded = nullptr;
-    bool pending = false;
+    // pinned staging of the descriptor table, a ring of kStage copies: a call
+    // waits only for the upload kStage calls back (normally long done)
+    static constexpr int kStage = 4;
+    BatchImage* h_stage[kStage] = {};
+    BatchDev* h_stage_hdr[kStage] = {};
+    hipEvent_t uploaded[kStage] = {};
+    bool pending[kStage] = {};
+    int next_stage = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -64,6 +71,7 @@ struct canny_batch_plan {
 namespace {
 
 constexpr int kT = 64;  // hysteresis tile rows
+constexpr double kTuneBudgetSeconds = 0.5;  // time box of one tuning run
 constexpr int kPerimT = 2 * kHystCols + 2 * kT;
 
 size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -146,14 +154,19 @@ hipError_t upload_sync(canny_batch_plan& p) {
 std::mutex g_tune_mu;
 std::map<std::string, int> g_tune_cache;
 
+// bucket of a positive quantity on a grid of 2^(1/steps) (steps per octave)
+int log_bucket(double v, int steps) { return v > 0.0 ? (int)std::floor(std::log2(v) * steps) : -1; }
+
 std::string tune_key(const canny_batch_plan& p) {
-    uint64_t h = 1469598103934665603ull;
+    double px = 0.0, sh = 0.0, sw = 0.0;
     for (const BatchImage& m : p.imgs) {
-        h = (h ^ (uint64_t)m.H) * 1099511628211ull;
-        h = (h ^ (uint64_t)m.W) * 1099511628211ull;
+        px += (double)m.H * m.W;
+        sh += m.H;
+        sw += m.W;
     }
     char buf[96];
-    std::snprintf(buf, sizeof(buf), "gfx950:%d:%d:%016llx", p.cus, p.n, (unsigned long long)h);
+    std::snprintf(buf, sizeof(buf), "gfx950:%d:n%d:px%d:h%d:w%d", p.cus, log_bucket(p.n, 2),
+                  log_bucket(px, 4), log_bucket(sh / p.n, 2), log_bucket(sw / p.n, 2));
     return buf;
 }
 
@@ -222,9 +235,17 @@ hipError_t autotune(canny_batch_plan& p) {
         p.hdr.ws = ws;
         float best = 1e30f;
         int best_rows = 32;
-        const int cand_rows[] = {16, 32, 48, 64};
+        // taller blocks spread the 8 halo rows of each block over more output
+        // rows; shorter ones give more waves.  Candidates in order of how
+        // often they won, tried until the budget (wall clock, including the
+        // warm-up replay of each) runs out; the default is always timed.
+        const int cand_rows[] = {64, 96, 48, 128, 32};
+        const auto t_start = std::chrono::steady_clock::now();
         for (int r : cand_rows) {
             if (e != hipSuccess) break;
+            const double spent =
+                std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+            if (r != cand_rows[0] && spent > kTuneBudgetSeconds) break;
             set_fwd_rows(p, r);
             e = upload_sync(p);
             float t = 1e30f;
@@ -265,12 +286,14 @@ void release(canny_batch_plan* p) {
     if (!p) return;
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
-    if (p->uploaded) (void)hipEventDestroy(p->uploaded);
+    for (int k = 0; k < canny_batch_plan::kStage; ++k) {
+        if (p->uploaded[k]) (void)hipEventDestroy(p->uploaded[k]);
+        if (p->h_stage[k]) (void)hipHostFree(p->h_stage[k]);
+        if (p->h_stage_hdr[k]) (void)hipHostFree(p->h_stage_hdr[k]);
+    }
     if (p->d_imgs) (void)hipFree(p->d_imgs);
     if (p->d_hdr) (void)hipFree(p->d_hdr);
     if (p->d_tile_img) (void)hipFree(p->d_tile_img);
-    if (p->h_stage) (void)hipHostFree(p->h_stage);
-    if (p->h_stage_hdr) (void)hipHostFree(p->h_stage_hdr);
     delete p;
 }
 
@@ -321,9 +344,11 @@ int canny_batch_plan_create(int n, const int32_t* H, const int32_t* W, int32_t l
             e = hipMemcpy(p->d_tile_img, ti.data(), sizeof(int32_t) * ti.size(), hipMemcpyHostToDevice);
         p->hdr.tile_img = p->d_tile_img;
     }
-    if (e == hipSuccess) e = hipHostMalloc(&p->h_stage, sizeof(BatchImage) * n, hipHostMallocDefault);
-    if (e == hipSuccess) e = hipHostMalloc(&p->h_stage_hdr, sizeof(BatchDev), hipHostMallocDefault);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->uploaded, hipEventDisableTiming);
+    for (int k = 0; k < canny_batch_plan::kStage && e == hipSuccess; ++k) {
+        e = hipHostMalloc(&p->h_stage[k], sizeof(BatchImage) * n, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipHostMalloc(&p->h_stage_hdr[k], sizeof(BatchDev), hipHostMallocDefault);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&p->uploaded[k], hipEventDisableTiming);
+    }
     if (e == hipSuccess && autotune_flag) e = autotune(*p);
     hipStream_t cs = nullptr;
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
@@ -373,23 +398,25 @@ int canny_batch(canny_batch_plan* p, const uint8_t* const* in, const int64_t* in
     }
     if (!ws || ws_bytes < p->ws_bytes || ((uintptr_t)ws % 256)) return CANNY_ERR_WORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    // the previous call's upload must have read the staging table
-    if (p->pending && hipEventSynchronize(p->uploaded) != hipSuccess) return CANNY_ERR_HIP;
+    // this call's staging copy was last read by the upload kStage calls ago
+    const int k = p->next_stage;
+    p->next_stage = (k + 1) % canny_batch_plan::kStage;
+    if (p->pending[k] && hipEventSynchronize(p->uploaded[k]) != hipSuccess) return CANNY_ERR_HIP;
+    BatchImage* st = p->h_stage[k];
     for (int i = 0; i < p->n; ++i) {
-        p->h_stage[i] = p->imgs[i];
-        p->h_stage[i].in = in[i];
-        p->h_stage[i].pitch = in_pitch[i];
-        p->h_stage[i].edges = edges[i];
-        p->h_stage[i].epitch = edges_pitch[i];
+        st[i] = p->imgs[i];
+        st[i].in = in[i];
+        st[i].pitch = in_pitch[i];
+        st[i].edges = edges[i];
+        st[i].epitch = edges_pitch[i];
     }
-    *p->h_stage_hdr = p->hdr;
-    p->h_stage_hdr->ws = static_cast<char*>(ws);
-    hipError_t e = hipMemcpyAsync(p->d_imgs, p->h_stage, sizeof(BatchImage) * p->n,
-                                  hipMemcpyHostToDevice, s);
+    *p->h_stage_hdr[k] = p->hdr;
+    p->h_stage_hdr[k]->ws = static_cast<char*>(ws);
+    hipError_t e = hipMemcpyAsync(p->d_imgs, st, sizeof(BatchImage) * p->n, hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(p->d_hdr, p->h_stage_hdr, sizeof(BatchDev), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipEventRecord(p->uploaded, s);
-    if (e == hipSuccess) p->pending = true;
+        e = hipMemcpyAsync(p->d_hdr, p->h_stage_hdr[k], sizeof(BatchDev), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipEventRecord(p->uploaded[k], s);
+    if (e == hipSuccess) p->pending[k] = true;
     if (e == hipSuccess) e = hipGraphLaunch(p->exec, s);
     return e == hipSuccess ? CANNY_OK : CANNY_ERR_HIP;
 }

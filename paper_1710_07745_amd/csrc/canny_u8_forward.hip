@@ -356,16 +356,17 @@ hipError_t launch_u8_forward_batch(const BatchImage* imgs, const BatchDev* hdr, 
                                    hipStream_t s) {
     const int nwg = max(ceil_div(total_fwd, kWavesPerWG), 1);
     switch (rows) {
-        case 16: hipLaunchKernelGGL(k_u8_forward_batch<16>, dim3(nwg), dim3(kWGThreads), 0, s, imgs, hdr); break;
         case 48: hipLaunchKernelGGL(k_u8_forward_batch<48>, dim3(nwg), dim3(kWGThreads), 0, s, imgs, hdr); break;
         case 64: hipLaunchKernelGGL(k_u8_forward_batch<64>, dim3(nwg), dim3(kWGThreads), 0, s, imgs, hdr); break;
+        case 96: hipLaunchKernelGGL(k_u8_forward_batch<96>, dim3(nwg), dim3(kWGThreads), 0, s, imgs, hdr); break;
+        case 128: hipLaunchKernelGGL(k_u8_forward_batch<128>, dim3(nwg), dim3(kWGThreads), 0, s, imgs, hdr); break;
         default: hipLaunchKernelGGL(k_u8_forward_batch<32>, dim3(nwg), dim3(kWGThreads), 0, s, imgs, hdr); break;
     }
     return hipGetLastError();
 }
 
 int u8_forward_supported_rows(int rows) {
-    return rows == 16 || rows == 32 || rows == 48 || rows == 64;
+    return rows == 32 || rows == 48 || rows == 64 || rows == 96 || rows == 128;
 }
 
 template <int R>
@@ -413,9 +414,9 @@ static bool u8_plan_ok(const U8Plan& p, int H, int W, int fast_ok) {
            (int64_t)p.sr * kU8StripCols + 4 <= W;  // last interior strip is sr - 1
 }
 
-// rows_per_wave <= 0: the balanced split (32-row blocks everywhere when it
-// would give fewer than 1024 waves, one per SIMD); otherwise that block
-// height for every strip.
+// The balanced split (32-row blocks everywhere when it would give fewer than
+// 1024 waves, one per SIMD); rows_per_wave > 0 asks for 32-row blocks
+// everywhere.
 hipError_t launch_u8_forward(const U8FwdArgs& a, int rows_per_wave, hipStream_t s) {
     if (rows_per_wave <= 0) {
         const int fast_ok = ((uintptr_t)a.in % 4 == 0) && (a.pitch % 4 == 0);
@@ -425,12 +426,7 @@ hipError_t launch_u8_forward(const U8FwdArgs& a, int rows_per_wave, hipStream_t 
                            dim3(kWGThreads), 0, s, a, p, fast_ok);
         return hipGetLastError();
     }
-    switch (rows_per_wave) {
-        case 16: return launch_r<16>(a, s);
-        case 48: return launch_r<48>(a, s);
-        case 64: return launch_r<64>(a, s);
-        default: return launch_r<32>(a, s);
-    }
+    return launch_r<32>(a, s);
 }
 
 }  // namespace canny

@@ -2,15 +2,16 @@
 // paper's stated direction of high-resolution image and video work; the
 // operator per frame is canny_u8, Section 2.2.1 Steps 1-4).
 //
-// A ring of `depth` device slots (input frame, edge map, workspace) and three
-// streams: frame k is copied host-to-device on the upload stream, detected on
-// the compute stream after the upload's event, and its edge map copied back on
-// the download stream after the detection's event.  A slot is reused only
-// after its previous download has finished (the upload waits on that event),
-// so with depth >= 3 the upload of frame k+1, the detection of frame k and the
-// download of frame k-1 run at the same time.  All waits are device-side; a
-// push returns at once (the copies are asynchronous when the host buffers are
-// pinned).  Every stream is created at the default priority.
+// A ring of `depth` device slots (input frame, edge map, workspace), each
+// with its own stream: frame k goes to slot k mod depth, and its
+// host-to-device copy, canny_u8 and device-to-host copy are enqueued on that
+// slot's stream.  The stream orders a slot's reuse after its previous frame
+// (no events, no cross-stream waits), and different slots' streams run
+// concurrently, so with depth >= 3 the upload of one frame, the detection of
+// another and the download of a third overlap.  A push is seven runtime calls
+// (two copies and canny_u8's five launches) and returns at once; the copies
+// are asynchronous when the host buffers are pinned.  Every stream is
+// created at the default priority.
 #include <hip/hip_runtime.h>
 
 #include <vector>
@@ -26,13 +27,11 @@ struct canny_video {
     int H = 0, W = 0, depth = 0;
     int32_t low = 0, high = 0;
     size_t ws_bytes = 0;
-    hipStream_t up = nullptr, comp = nullptr, down = nullptr;
     struct Slot {
         uint8_t* in = nullptr;
         uint8_t* edges = nullptr;
         void* ws = nullptr;
-        hipEvent_t uploaded = nullptr, detected = nullptr, downloaded = nullptr;
-        bool used = false;
+        hipStream_t stream = nullptr;
     };
     std::vector<Slot> slots;
     int64_t next = 0;
@@ -48,13 +47,8 @@ void release(canny_video* v) {
         if (s.in) (void)hipFree(s.in);
         if (s.edges) (void)hipFree(s.edges);
         if (s.ws) (void)hipFree(s.ws);
-        if (s.uploaded) (void)hipEventDestroy(s.uploaded);
-        if (s.detected) (void)hipEventDestroy(s.detected);
-        if (s.downloaded) (void)hipEventDestroy(s.downloaded);
+        if (s.stream) (void)hipStreamDestroy(s.stream);
     }
-    if (v->up) (void)hipStreamDestroy(v->up);
-    if (v->comp) (void)hipStreamDestroy(v->comp);
-    if (v->down) (void)hipStreamDestroy(v->down);
     delete v;
 }
 
@@ -77,17 +71,13 @@ int canny_video_create(int H, int W, int32_t low, int32_t high, int depth, canny
     v->high = high;
     v->ws_bytes = canny_u8_workspace_bytes(H, W);
     const size_t frame = (size_t)H * W;
-    hipError_t e = hipStreamCreateWithFlags(&v->up, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&v->comp, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&v->down, hipStreamNonBlocking);
+    hipError_t e = hipSuccess;
     v->slots.resize(depth);
     for (auto& s : v->slots) {
         if (e == hipSuccess) e = hipMalloc(&s.in, frame);
         if (e == hipSuccess) e = hipMalloc(&s.edges, frame);
         if (e == hipSuccess) e = hipMalloc(&s.ws, v->ws_bytes);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&s.uploaded, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&s.detected, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&s.downloaded, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking);
     }
     if (e != hipSuccess) {
         release(v);
@@ -101,31 +91,23 @@ int canny_video_push(canny_video* v, const uint8_t* host_frame, uint8_t* host_ed
     if (!v || !host_frame || !host_edges) return CANNY_ERR_INVALID;
     canny_video::Slot& s = v->slots[(size_t)(v->next % v->depth)];
     const size_t frame = (size_t)v->H * v->W;
-    hipError_t e = hipSuccess;
-    // the slot's previous frame must be downloaded before its buffers are reused
-    if (s.used) e = hipStreamWaitEvent(v->up, s.downloaded, 0);
-    if (e == hipSuccess) e = hipMemcpyAsync(s.in, host_frame, frame, hipMemcpyHostToDevice, v->up);
-    if (e == hipSuccess) e = hipEventRecord(s.uploaded, v->up);
-    if (e == hipSuccess) e = hipStreamWaitEvent(v->comp, s.uploaded, 0);
-    if (e != hipSuccess) return CANNY_ERR_HIP;
+    // the slot's stream runs its previous frame's download before this upload
+    if (hipMemcpyAsync(s.in, host_frame, frame, hipMemcpyHostToDevice, s.stream) != hipSuccess)
+        return CANNY_ERR_HIP;
     const int st = canny_u8(s.in, v->W, v->H, v->W, v->low, v->high, s.edges, v->W, nullptr, s.ws,
-                            v->ws_bytes, v->comp);
+                            v->ws_bytes, s.stream);
     if (st != CANNY_OK) return st;
-    e = hipEventRecord(s.detected, v->comp);
-    if (e == hipSuccess) e = hipStreamWaitEvent(v->down, s.detected, 0);
-    if (e == hipSuccess) e = hipMemcpyAsync(host_edges, s.edges, frame, hipMemcpyDeviceToHost, v->down);
-    if (e == hipSuccess) e = hipEventRecord(s.downloaded, v->down);
-    if (e != hipSuccess) return CANNY_ERR_HIP;
-    s.used = true;
+    if (hipMemcpyAsync(host_edges, s.edges, frame, hipMemcpyDeviceToHost, s.stream) != hipSuccess)
+        return CANNY_ERR_HIP;
     ++v->next;
     return CANNY_OK;
 }
 
 int canny_video_sync(canny_video* v) {
     if (!v) return CANNY_ERR_INVALID;
-    hipError_t e = hipStreamSynchronize(v->up);
-    if (e == hipSuccess) e = hipStreamSynchronize(v->comp);
-    if (e == hipSuccess) e = hipStreamSynchronize(v->down);
+    hipError_t e = hipSuccess;
+    for (auto& s : v->slots)
+        if (e == hipSuccess) e = hipStreamSynchronize(s.stream);
     return e == hipSuccess ? CANNY_OK : CANNY_ERR_HIP;
 }
 
