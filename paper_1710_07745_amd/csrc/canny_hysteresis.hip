@@ -154,10 +154,38 @@ struct TileLabel {
     uint64_t m, S;          // candidate and run-start bits of this thread's row
 };
 
-// Load this thread's class codes and label the tile's candidates in LDS:
-// afterwards L[r*64 + s] is the root (smallest index) of the component of
-// the run that starts at column s of row r; only run starts carry entries.
-// cm holds the 64-bit candidate mask of every tile row.
+// L[i] for a run start i: the pixel index of its root (bits 0..11) once the
+// labels are final.  A root's own entry then also carries 1 + b in bits
+// 17..24, b the largest border pixel index of its component (0: the
+// component does not touch the tile border); whether the component holds a
+// strong pixel is a separate bitmap, one bit per root.
+constexpr int kRootMask = 0xFFFF;
+constexpr int kBrepShift = 17;
+
+// largest border pixel index (see border_index) of the run of row r covering
+// columns c0..c1 in a tile clipped to th x tw, or -1 if it has none; a
+// one-column tile's pixels count as the left column, as in border_index
+__device__ __forceinline__ int run_border_max(int r, int c0, int c1, int th, int tw) {
+    if (r == 0) return c1;
+    if (r == th - 1) return kHystCols + c1;
+    if (c1 == tw - 1 && c1 != 0) return 3 * kHystCols - 3 + r;
+    if (c0 == 0) return 2 * kHystCols - 1 + r;
+    return -1;
+}
+
+// Load this thread's class codes and label the tile's candidates in LDS.
+// Afterwards L[r*64 + s] holds the root (smallest index) of the component
+// of the run that starts at column s of row r (only run starts carry
+// entries), every root's entry carries its component's largest border index
+// and `strong` its strong bit.  cm and smk hold the 64-bit candidate and
+// strong masks of every tile row.
+//   phase 1: codes, row masks, and each run start's L entry (a run's start
+//            needs only the pixel before this thread's segment, a lane away)
+//   phase 2: the unions with the row above
+//   phase 3: each run start walks to its root and stores it; a run with a
+//            strong pixel sets its root's strong bit, and a run on the tile
+//            border raises its root's border index -- per run, from the
+//            run's extent, instead of per pixel
 // Class codes (2 bits per pixel, pixel k at bits 2k) of 16 pixels of the
 // signed strength map: kept (value > 0) and > hi -> 2, kept and >= lo -> 1.
 // nquads >= 1: the four loads are unconditional (quads past nquads re-read
@@ -181,7 +209,7 @@ __device__ __forceinline__ uint32_t codes_from_signed(const float* row, int nqua
 
 template <int T>
 __device__ __forceinline__ TileLabel<T> tile_label(const HystArgs& a, const TileGeom& g, int* L,
-                                                   uint64_t* cm) {
+                                                   uint64_t* cm, uint64_t* smk, uint32_t* strong) {
     using TL = Tile<T>;
     static_assert(TL::kPPT == 16, "row masks assume 16-pixel segments");
     const int W = a.W;
@@ -216,16 +244,21 @@ __device__ __forceinline__ TileLabel<T> tile_label(const HystArgs& a, const Tile
     st.cand = compress2(codes | (codes >> 1));
     st.strong = compress2((codes >> 1) & ~codes);  // code 2
     reinterpret_cast<uint16_t*>(cm)[r * 4 + seg] = (uint16_t)st.cand;
+    reinterpret_cast<uint16_t*>(smk)[r * 4 + seg] = (uint16_t)st.strong;
+    // run starts of this segment: the pixel before it is the top bit of the
+    // previous lane's segment (same row unless this is the row's first)
+    const uint32_t left = from_left(st.cand);
+    const uint32_t before = seg == 0 ? 0u : (left >> 15) & 1u;
+    const uint32_t s16 = st.cand & ~((st.cand << 1) | before);
+    for (uint32_t b = s16; b; b &= b - 1) {
+        const int i = r * kHystCols + cb + __ffs(b) - 1;
+        L[i] = i;
+    }
     __syncthreads();
     st.m = cm[r];
     st.S = st.m & ~(st.m << 1);
     const uint64_t segmask = 0xFFFFull << cb;
     const uint64_t Smine = st.S & segmask;
-    for (uint64_t b = Smine; b; b &= b - 1) {
-        const int i = r * kHystCols + __ffsll((long long)b) - 1;
-        L[i] = i;
-    }
-    __syncthreads();
     if (r > 0 && (st.m & segmask)) {  // runs may start in an earlier segment
         const uint64_t A = cm[r - 1];
         const uint64_t SA = A & ~(A << 1);
@@ -248,19 +281,29 @@ __device__ __forceinline__ TileLabel<T> tile_label(const HystArgs& a, const Tile
     }
     __syncthreads();
     // all unions are in: each run start walks to its root (pointers only
-    // decrease, so within i + 1 steps) and stores it.  Concurrent walks read
-    // either an old pointer (an ancestor) or a root, so no store can mislead
-    // another walk.
+    // decrease, so within i + 1 steps).  A walk reads either an old pointer (an
+    // ancestor), a root, or a root entry whose border bits another run has
+    // already raised, hence the mask; a run start that is itself a root keeps
+    // its entry (another run may be raising its border bits).
     volatile lds_i32* V = lds_volatile(L);
+    const uint64_t srow = smk[r];
     for (uint64_t b = Smine; b; b &= b - 1) {
-        const int i = r * kHystCols + __ffsll((long long)b) - 1;
-        int x = V[i];
+        const int c0 = __ffsll((long long)b) - 1;
+        const int i = r * kHystCols + c0;
+        int x = V[i] & kRootMask;
         for (int steps = i; steps >= 0; --steps) {
-            const int p = V[x];
+            const int p = V[x] & kRootMask;
             if (p == x) break;
             x = p;
         }
-        V[i] = x;
+        if (x != i) V[i] = x;
+        // the run covers columns c0 .. c1 (its first 0 bit above c0, minus one)
+        const uint64_t rest = ~st.m >> c0;
+        const int c1 = c0 + (rest ? __ffsll((long long)rest) - 1 : 64 - c0) - 1;
+        const uint64_t span = (c1 - c0 >= 63) ? ~0ull : (((2ull << (c1 - c0)) - 1ull) << c0);
+        if (srow & span) atomicOr(&strong[x >> 5], 1u << (x & 31));
+        const int bmax = run_border_max(r, c0, c1, g.th, g.tw);
+        if (bmax >= 0) atomicMax(&L[x], x | ((1 + bmax) << kBrepShift));
     }
     __syncthreads();
     return st;
@@ -275,21 +318,16 @@ __device__ __forceinline__ void for_slots(int r, int c, int th, int tw, F f) {
     if (c == tw - 1) f(2 * kHystCols + T + r);
 }
 
-// L[i] for a run start i: the pixel index of its root (bits 0..11) once the
-// labels are final.  A root's own entry then also carries its component's
-// flags: bit 16 = holds a strong pixel, bits 17..24 = 1 + b for some border
-// pixel index b of the component (0: does not touch the tile border).
-constexpr int kRootMask = 0xFFFF;
-constexpr int kStrongBit = 1 << 16;
-constexpr int kBrepShift = 17;
 // global names of border components: tile * kNamesPerTile + border index
 constexpr int kNamesPerTile = 256;
 
 template <int T>
 struct LocalSmem {
     int L[Tile<T>::kPx];
-    uint64_t cm[T];               // candidate mask of each tile row
-    int bl[Tile<T>::kPerim];      // staged border names: one global store per slot
+    uint64_t cm[T];                  // candidate mask of each tile row
+    uint64_t smk[T];                 // strong mask of each tile row
+    uint32_t strong[Tile<T>::kPx / 32];  // strong bit of each root
+    int bl[Tile<T>::kPerim];         // staged border names: one global store per slot
 };
 
 // border pixel index b of tile pixel (r, c), or -1 inside (see the file comment)
@@ -397,49 +435,36 @@ __device__ __forceinline__ void local_tile(const HystArgs& a, int tile, int tile
     const TileGeom g = tile_geom<T>(tile, tiles_x, a.H, a.W);
     const int t = threadIdx.x;
     for (int s = t; s < TL::kPerim; s += kWGThreads) bl[s] = -1;  // "no candidate"
+    for (int w = t; w < TL::kPx / 32; w += kWGThreads) sm.strong[w] = 0u;
     if (a.max_out && tile == 0 && t == 0) *a.max_out = __uint_as_float(*a.maxbits);
-    const TileLabel<T> st = tile_label<T>(a, g, L, sm.cm);
+    const TileLabel<T> st = tile_label<T>(a, g, L, sm.cm, sm.smk, sm.strong);
     const int r = t / TL::kTPR;
     const int cb = (t % TL::kTPR) * TL::kPPT;
     const int me = r * kHystCols;
-    for (uint32_t b = st.strong; b; b &= b - 1) {
-        const int c = cb + __ffs(b) - 1;
-        atomicOr(&L[L[me + run_start(st.S, c)] & kRootMask], kStrongBit);
-    }
-    __syncthreads();
-    // border pixels point their component at its largest border index
+    // every candidate: 255 / 0 for a component inside the tile (by its strong
+    // bit), the pending code 1 + b for one that touches the border (b its
+    // largest border index); border pixels also stage the component's global
+    // name, and the one at index b starts its union-find entry
     const bool border_seg = r == 0 || r == g.th - 1 || cb == 0 || cb + TL::kPPT >= g.tw;
-    if (border_seg) {
-        for (uint32_t b = st.cand; b; b &= b - 1) {
-            const int c = cb + __ffs(b) - 1;
-            const int bi = border_index(r, c, g.th, g.tw);
-            if (bi < 0) continue;
-            const int root = L[me + run_start(st.S, c)] & kRootMask;
-            const int low = root | (L[root] & kStrongBit);  // final: no strong marks remain
-            atomicMax(&L[root], low | ((1 + bi) << kBrepShift));  // the largest index wins
-        }
-    }
-    __syncthreads();
     bool pending = false;
     if (r < g.th) {
         Seg16 out;
         const int nbase = g.tile * kNamesPerTile;
         for (uint32_t b = st.cand; b; b &= b - 1) {
             const int k = __ffs(b) - 1;
-            const int v = L[L[me + run_start(st.S, cb + k)] & kRootMask];
-            const uint32_t br = (uint32_t)v >> kBrepShift;
+            const int root = L[me + run_start(st.S, cb + k)] & kRootMask;
+            const uint32_t br = (uint32_t)L[root] >> kBrepShift;
+            const bool strong = (sm.strong[root >> 5] >> (root & 31)) & 1u;
             pending |= br != 0;
-            out.set(k, br ? br : ((v & kStrongBit) ? 255u : 0u));
+            out.set(k, br ? br : (strong ? 255u : 0u));
             if (border_seg && br) {
-                // the component's global name, in this pixel's border slots;
-                // the representative pixel itself starts the union-find entry
                 const int bi = border_index(r, cb + k, g.th, g.tw);
                 if (bi < 0) continue;
                 const int name = nbase + (int)br - 1;
                 for_slots<T>(r, cb + k, g.th, g.tw, [&](int s) { bl[s] = name; });
                 if (bi == (int)br - 1) {
                     a.parent[name] = name;
-                    a.flag[name] = (v & kStrongBit) ? 1 : 0;
+                    a.flag[name] = strong ? 1 : 0;
                 }
             }
         }
