@@ -20,6 +20,10 @@
 //   input row -> horizontal binomial (5-row window) -> vertical binomial +
 //   rounding (B) and its horizontal second difference (3-row window) ->
 //   L (3-row window) -> crossing masks -> 4 edge bytes per lane.
+// Each pair of 4-neighbours is tested once (horizontal pairs within the row,
+// the vertical pair with the row below, whose mark for the lower pixel is
+// carried to the next row), which costs about half of testing all four
+// neighbours from every pixel.
 // All arithmetic is packed 16-bit: |L| <= 1020, |L(p)| + |L(q)| <= 2040.
 #include "canny_internal.h"
 #include "canny_u8_common.h"
@@ -27,37 +31,43 @@
 namespace canny {
 namespace {
 
-__device__ __forceinline__ i16x2 ashr15(i16x2 v) { return v >> (i16x2){15, 15}; }
-
-// sign masks (all ones in a half where the value is < 0 / > 0) and |v|
+// The crossing logic carries every decision in bit 15 of each 16-bit half
+// (the sign bit of a packed value); the other bits are don't-cares.  So a
+// negative test is the value itself, a positive test is its negation, and
+// "a < b" is a - b: no shifts, no compares, no selects.  (Spelled as masks,
+// x >> 15 & y, the compiler turned every test into per-element compares and
+// selects.)  Only the final conversion to 0xFF / 0x00 per pixel shifts.
 struct Sgn {
-    i16x2 neg, pos, abs;
+    i16x2 v, p, a;  // v: bit 15 iff < 0; p = -v: bit 15 iff > 0; a = |v|
 };
 __device__ __forceinline__ Sgn sgn(i16x2 v) {
     const i16x2 nv = (i16x2){0, 0} - v;
-    return {ashr15(v), ashr15(nv), __builtin_elementwise_max(v, nv)};
+    return {v, nv, __builtin_elementwise_max(v, nv)};
 }
 
-// strictly opposite signs, and |a - b| = |a| + |b| >= t (masks per half)
+// bit 15: strictly opposite signs, and |a - b| = |a| + |b| >= t
 __device__ __forceinline__ i16x2 crosses(const Sgn& a, const Sgn& b, i16x2 t2) {
-    const i16x2 opp = (a.neg & b.pos) | (a.pos & b.neg);
-    return opp & ~ashr15(a.abs + b.abs - t2);
+    const i16x2 opp = (a.v & b.p) | (a.p & b.v);
+    return opp & ~(a.a + b.a - t2);
 }
 
-// Edge masks of two pixels c (x, x+1) with their neighbours on the left
-// (x-1, x), right (x+1, x+2), above and below.
-__device__ __forceinline__ uint32_t edge_mask(i16x2 c, i16x2 l, i16x2 r, i16x2 u, i16x2 d, i16x2 t2) {
-    const Sgn sc = sgn(c), sl = sgn(l), sr = sgn(r), su = sgn(u), sd = sgn(d);
-    // (a) the pair with a later neighbour marks c when |c| <= |q|, with an
-    // earlier neighbour when |c| < |q|
-    i16x2 m = crosses(sc, sr, t2) & ~ashr15(sr.abs - sc.abs);
-    m |= crosses(sc, sd, t2) & ~ashr15(sd.abs - sc.abs);
-    m |= crosses(sc, sl, t2) & ashr15(sc.abs - sl.abs);
-    m |= crosses(sc, su, t2) & ashr15(sc.abs - su.abs);
-    // (b) c = 0 between opposite neighbours
-    const i16x2 zero = ~(sc.neg | sc.pos);
-    m |= zero & (crosses(sl, sr, t2) | crosses(su, sd, t2));
-    return W32(m);
+// bit 15 of each half -> 0xFFFF / 0x0000.  op_sel_hi:[0,1]: the high half's
+// shift amount is the constant's low half too (by default it would read the
+// constant's high 16 bits, 0, and leave the high half unshifted).
+__device__ __forceinline__ uint32_t full_mask(uint32_t m) {
+    uint32_t r;
+    __asm__("v_pk_ashrrev_i16 %0, 15, %1 op_sel_hi:[0,1]" : "=v"(r) : "v"(m));
+    return r;
+}
+
+// a lane's two packed registers (x, x+1), (x+2, x+3) moved one pixel: to the
+// right neighbours (x+1, x+2), (x+3, x+4), or to the left ones (x-1, x)
+__device__ __forceinline__ void to_right(uint32_t v0, uint32_t v1, uint32_t& r0, uint32_t& r1) {
+    r0 = align16(v1, v0);
+    r1 = align16(from_right(v0), v1);
+}
+__device__ __forceinline__ uint32_t to_left0(uint32_t v0, uint32_t v1) {
+    return align16(v0, from_left(v1));
 }
 
 template <int R, bool BORDER>
@@ -101,6 +111,7 @@ __device__ __forceinline__ void log_walk(const LogArgs& a, int X0, int Y0, int l
     uint32_t hw0[5], hw1[5];                      // horizontal blur, rows vi-4 .. vi
     uint32_t bw0[3], bw1[3], xw0[3], xw1[3];      // B and its x second difference, rows b-2 .. b
     uint32_t lw0[3], lw1[3];                      // L, rows g-2 .. g
+    uint32_t down0 = 0, down1 = 0;                // marks of row n from the pair (n-1, n)
 
 #pragma unroll
     for (int i = 0; i < R + 8; ++i) {
@@ -154,14 +165,50 @@ __device__ __forceinline__ void log_walk(const LogArgs& a, int X0, int Y0, int l
         if (BORDER && g == 0) { lw0[0] = lw0[1] = L0; lw1[0] = lw1[1] = L1; }
         if (i < 8) continue;
 
-        // ---- zero crossings of row n = g - 1
+        // ---- zero crossings of row n = g - 1.  Each pair of 4-neighbours is
+        // tested once, and its mark goes to the pixel nearer the zero (the
+        // earlier one on a tie): horizontal pairs (x, x+1) of this row, the
+        // vertical pair (n, n+1); the mark of (n-1, n) for row n comes from
+        // the previous row's test (or, for the wave's first row, is tested
+        // here).  Then the zeros between opposite neighbours.
         const int n = g - 1;
         if (BORDER && n >= H) continue;
+        const Sgn c0s = sgn(S(lw0[1])), c1s = sgn(S(lw1[1]));
+        const Sgn u0s = sgn(S(lw0[0])), u1s = sgn(S(lw1[0]));
+        const Sgn d0s = sgn(S(lw0[2])), d1s = sgn(S(lw1[2]));
+        // right neighbours (x+1, x+2), (x+3, x+4) and left ones (x-1, x)
+        uint32_t rn0, rn1, rp0, rp1, ra0, ra1;
+        to_right(W32(c0s.v), W32(c1s.v), rn0, rn1);
+        to_right(W32(c0s.p), W32(c1s.p), rp0, rp1);
+        to_right(W32(c0s.a), W32(c1s.a), ra0, ra1);
+        const Sgn r0s = {S(rn0), S(rp0), S(ra0)}, r1s = {S(rn1), S(rp1), S(ra1)};
+        const Sgn l0s = {S(to_left0(W32(c0s.v), W32(c1s.v))), S(to_left0(W32(c0s.p), W32(c1s.p))),
+                         S(to_left0(W32(c0s.a), W32(c1s.a)))};
+        // horizontal pairs starting at each pixel; the right pixel wins when
+        // its |L| is strictly smaller (bit 15 of r.a - c.a)
+        const i16x2 h0 = crosses(c0s, r0s, t2), h1 = crosses(c1s, r1s, t2);
+        const i16x2 rw0 = r0s.a - c0s.a, rw1 = r1s.a - c1s.a;
+        const uint32_t mR0 = W32(h0 & rw0), mR1 = W32(h1 & rw1);
+        uint32_t m0 = W32(h0 & ~rw0) | align16(mR0, from_left(mR1));
+        uint32_t m1 = W32(h1 & ~rw1) | align16(mR1, mR0);
+        // vertical pair (n, n+1): the lower pixel wins when strictly smaller
+        const i16x2 v0 = crosses(c0s, d0s, t2), v1 = crosses(c1s, d1s, t2);
+        const i16x2 dw0 = d0s.a - c0s.a, dw1 = d1s.a - c1s.a;
+        if (i == 8) {  // the wave's first row: the pair (n-1, n) has not been tested
+            down0 = W32(crosses(u0s, c0s, t2) & (c0s.a - u0s.a));
+            down1 = W32(crosses(u1s, c1s, t2) & (c1s.a - u1s.a));
+        }
+        m0 |= W32(v0 & ~dw0) | down0;
+        m1 |= W32(v1 & ~dw1) | down1;
+        down0 = W32(v0 & dw0);
+        down1 = W32(v1 & dw1);
+        // zeros (neither sign bit of v nor of -v set) between strictly
+        // opposite left/right or upper/lower neighbours
+        m0 |= W32(~(c0s.v | c0s.p) & (crosses(l0s, r0s, t2) | crosses(u0s, d0s, t2)));
+        m1 |= W32(~(c1s.v | c1s.p) & (crosses(r0s, r1s, t2) | crosses(u1s, d1s, t2)));
+        m0 = full_mask(m0);
+        m1 = full_mask(m1);
         const uint32_t c0v = lw0[1], c1v = lw1[1];
-        const uint32_t cl = from_left(c1v), cr = from_right(c0v);
-        const uint32_t Lm1 = align16(c0v, cl), Lp1 = align16(c1v, c0v), Lp3 = align16(cr, c1v);
-        const uint32_t m0 = edge_mask(S(c0v), S(Lm1), S(Lp1), S(lw0[0]), S(lw0[2]), t2);
-        const uint32_t m1 = edge_mask(S(c1v), S(Lp1), S(Lp3), S(lw1[0]), S(lw1[2]), t2);
         const uint32_t bytes = perm(m1, m0, 0x07050301u);  // 0xFF / 0x00 per pixel
         if (store_lane) {
             uint8_t* erow = a.edges + (int64_t)n * a.epitch;
@@ -203,13 +250,61 @@ k_log_u8(LogArgs a, int strips_x, int nwaves, int fast_ok) {
     else log_walk<R, true>(a, X0, Y0, lane, fast_ok);
 }
 
+// Balanced launch (the integer forward's split, U8Plan): border blocks of
+// RRE rows, interior blocks of RRI, so the border waves (clamped loads,
+// per-stage replication) do not set the kernel's end.
+template <int RRI, int RRE>
+__global__ void __launch_bounds__(kWGThreads)
+k_log_u8_bal(LogArgs a, U8Plan p, int fast_ok) {
+    static_assert(RRE >= 4, "the top border block must cover the interior blocks' upper halo");
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave_in_wg = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wg = xcd_remap(blockIdx.x, gridDim.x);
+    const int wave = wg * kWavesPerWG + wave_in_wg;
+    if (wave >= p.nwaves) return;
+    int X0, Y0;
+    bool interior = false;
+    if (wave < p.edge_waves) {
+        const int es = wave % p.n_es;
+        X0 = (es == 0 ? 0 : p.sr + es - 1) * kU8StripCols;
+        Y0 = (wave / p.n_es) * RRE;
+    } else {
+        const int w = wave - p.edge_waves;
+        const int blk = w / p.n_is;
+        X0 = (1 + w % p.n_is) * kU8StripCols;
+        if (blk == 0) {
+            Y0 = 0;
+        } else if (blk <= p.k) {
+            Y0 = RRE + (blk - 1) * RRI;
+            interior = true;
+        } else {
+            Y0 = RRE + p.k * RRI + (blk - 1 - p.k) * RRE;
+        }
+    }
+    if (interior) {
+        if (!(fast_ok && X0 >= 4 && X0 + kU8StripCols + 4 <= a.W && Y0 >= 4 && Y0 + RRI + 4 <= a.H))
+            return;  // unreachable for a plan from make_u8_plan
+        log_walk<RRI, false>(a, X0, Y0, lane, true);
+    } else {
+        log_walk<RRE, true>(a, X0, Y0, lane, fast_ok);
+    }
+}
+
+constexpr int kLogRRI = 40, kLogRRE = 20;
+
 }  // namespace
 
 hipError_t launch_log_u8(const LogArgs& a, hipStream_t s) {
+    const int fast_ok = ((uintptr_t)a.in % 4 == 0) && (a.pitch % 4 == 0);
+    const U8Plan p = make_u8_plan(a.H, a.W, fast_ok, kLogRRI, kLogRRE);
+    if (p.nwaves >= 1024 && u8_plan_ok(p, a.H, a.W, fast_ok, kLogRRI, kLogRRE)) {
+        hipLaunchKernelGGL((k_log_u8_bal<kLogRRI, kLogRRE>), dim3(ceil_div(p.nwaves, kWavesPerWG)),
+                           dim3(kWGThreads), 0, s, a, p, fast_ok);
+        return hipGetLastError();
+    }
     const int strips_x = ceil_div(a.W, kU8StripCols);
     const int nwaves = strips_x * ceil_div(a.H, kLogRows);
     const int nwg = ceil_div(nwaves, kWavesPerWG);
-    const int fast_ok = ((uintptr_t)a.in % 4 == 0) && (a.pitch % 4 == 0);
     hipLaunchKernelGGL(k_log_u8<kLogRows>, dim3(nwg), dim3(kWGThreads), 0, s, a, strips_x, nwaves,
                        fast_ok);
     return hipGetLastError();

@@ -78,5 +78,52 @@ __device__ __forceinline__ void hblur(uint32_t d, uint32_t& h0, uint32_t& h1) {
     h1 = W32((E0 + E2) + (O0 + O1) * four + E1 * six);
 }
 
+// Balanced single-image launch.  A border wave (clamped loads, per-stage
+// replication) costs about 1.7x an interior wave per row, and with one block
+// height the border waves set the kernel's end; so border blocks are RRE rows
+// tall and interior blocks RRI > RRE.  Waves [0, edge_waves) walk the border
+// strips ({0} and [sr, strips_x), or every strip when rows are not 4-byte
+// aligned) block-major; the rest walk the interior strips [1, sr), each with
+// one border block at the top, k interior blocks from row RRE, and nb border
+// blocks below them.
+struct U8Plan {
+    int nwaves, edge_waves;
+    int n_es, sr, n_is;
+    int k, nb;
+};
+
+
+inline U8Plan make_u8_plan(int H, int W, int fast_ok, int RRI, int RRE) {
+    U8Plan p{};
+    const int strips_x = ceil_div(W, kU8StripCols);
+    int sr = strips_x;  // first strip whose right halo leaves the image
+    if (!fast_ok || strips_x == 1) {
+        sr = 1;
+    } else {
+        for (int s = 1; s < strips_x; ++s)
+            if ((int64_t)(s + 1) * kU8StripCols + 4 > W) {
+                sr = s;
+                break;
+            }
+    }
+    p.sr = sr;
+    p.n_es = 1 + (strips_x - sr);
+    p.n_is = sr - 1;
+    p.k = H >= 2 * RRE ? (H - 2 * RRE) / RRI : 0;
+    p.nb = ceil_div(max(0, H - RRE - p.k * RRI), RRE);
+    p.edge_waves = p.n_es * ceil_div(H, RRE);
+    p.nwaves = p.edge_waves + p.n_is * (1 + p.k + p.nb);
+    return p;
+}
+
+// The interior conditions the balanced kernel relies on, checked on the host
+// (they hold by construction): halo rows and columns of every interior block
+// inside the image, 4-byte aligned rows.
+inline bool u8_plan_ok(const U8Plan& p, int H, int W, int fast_ok, int RRI, int RRE) {
+    if (p.n_is == 0 || p.k == 0) return true;  // no interior block
+    return fast_ok && RRE >= 4 && RRE + p.k * RRI + 4 <= H &&
+           (int64_t)p.sr * kU8StripCols + 4 <= W;  // last interior strip is sr - 1
+}
+
 }  // namespace
 }  // namespace canny

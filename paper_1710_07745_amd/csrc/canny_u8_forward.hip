@@ -259,20 +259,6 @@ k_u8_forward(U8FwdArgs a, int strips_x, int nwaves, int fast_ok) {
     else walk<R, true>(a, X0, Y0, lane, fast_ok);
 }
 
-// Balanced single-image launch.  A border wave (clamped loads, per-stage
-// replication) costs about 1.7x an interior wave per row, and with one block
-// height the border waves set the kernel's end; so border blocks are RRE rows
-// tall and interior blocks RRI > RRE.  Waves [0, edge_waves) walk the border
-// strips ({0} and [sr, strips_x), or every strip when rows are not 4-byte
-// aligned) block-major; the rest walk the interior strips [1, sr), each with
-// one border block at the top, k interior blocks from row RRE, and nb border
-// blocks below them.
-struct U8Plan {
-    int nwaves, edge_waves;
-    int n_es, sr, n_is;
-    int k, nb;
-};
-
 template <int RRI, int RRE>
 __global__ void __launch_bounds__(kWGThreads)
 k_u8_forward_bal(U8FwdArgs a, U8Plan p, int fast_ok) {
@@ -382,46 +368,14 @@ static hipError_t launch_r(const U8FwdArgs& a, hipStream_t s) {
 
 constexpr int kU8RRI = 40, kU8RRE = 20;  // balanced block heights (interior, border)
 
-static U8Plan make_u8_plan(int H, int W, int fast_ok) {
-    U8Plan p{};
-    const int strips_x = ceil_div(W, kU8StripCols);
-    int sr = strips_x;  // first strip whose right halo leaves the image
-    if (!fast_ok || strips_x == 1) {
-        sr = 1;
-    } else {
-        for (int s = 1; s < strips_x; ++s)
-            if ((int64_t)(s + 1) * kU8StripCols + 4 > W) {
-                sr = s;
-                break;
-            }
-    }
-    p.sr = sr;
-    p.n_es = 1 + (strips_x - sr);
-    p.n_is = sr - 1;
-    p.k = H >= 2 * kU8RRE ? (H - 2 * kU8RRE) / kU8RRI : 0;
-    p.nb = ceil_div(max(0, H - kU8RRE - p.k * kU8RRI), kU8RRE);
-    p.edge_waves = p.n_es * ceil_div(H, kU8RRE);
-    p.nwaves = p.edge_waves + p.n_is * (1 + p.k + p.nb);
-    return p;
-}
-
-// The interior conditions the balanced kernel relies on, checked on the host
-// (they hold by construction): halo rows and columns of every interior block
-// inside the image, 4-byte aligned rows.
-static bool u8_plan_ok(const U8Plan& p, int H, int W, int fast_ok) {
-    if (p.n_is == 0 || p.k == 0) return true;  // no interior block
-    return fast_ok && kU8RRE >= 4 && kU8RRE + p.k * kU8RRI + 4 <= H &&
-           (int64_t)p.sr * kU8StripCols + 4 <= W;  // last interior strip is sr - 1
-}
-
 // The balanced split (32-row blocks everywhere when it would give fewer than
 // 1024 waves, one per SIMD); rows_per_wave > 0 asks for 32-row blocks
 // everywhere.
 hipError_t launch_u8_forward(const U8FwdArgs& a, int rows_per_wave, hipStream_t s) {
     if (rows_per_wave <= 0) {
         const int fast_ok = ((uintptr_t)a.in % 4 == 0) && (a.pitch % 4 == 0);
-        const U8Plan p = make_u8_plan(a.H, a.W, fast_ok);
-        if (p.nwaves < 1024 || !u8_plan_ok(p, a.H, a.W, fast_ok)) return launch_r<32>(a, s);
+        const U8Plan p = make_u8_plan(a.H, a.W, fast_ok, kU8RRI, kU8RRE);
+        if (p.nwaves < 1024 || !u8_plan_ok(p, a.H, a.W, fast_ok, kU8RRI, kU8RRE)) return launch_r<32>(a, s);
         hipLaunchKernelGGL((k_u8_forward_bal<kU8RRI, kU8RRE>), dim3(ceil_div(p.nwaves, kWavesPerWG)),
                            dim3(kWGThreads), 0, s, a, p, fast_ok);
         return hipGetLastError();
