@@ -186,60 +186,86 @@ __device__ __forceinline__ int run_border_max(int r, int c0, int c1, int th, int
 //            strong pixel sets its root's strong bit, and a run on the tile
 //            border raises its root's border index -- per run, from the
 //            run's extent, instead of per pixel
-// Class codes (2 bits per pixel, pixel k at bits 2k) of 16 pixels of the
-// signed strength map: kept (value > 0) and > hi -> 2, kept and >= lo -> 1.
-// nquads >= 1: the four loads are unconditional (quads past nquads re-read
-// the last one and are masked), so all are in flight together.
-__device__ __forceinline__ uint32_t codes_from_signed(const float* row, int nquads, float lo, float hi) {
-    float4 v[4];
+// A thread's 16 pixels as loaded, before classification: four quads of the
+// signed strength map (float path) or one dword of the class map.  The
+// loads are unconditional inside the row (quads past nq re-read the last one
+// and are masked later), so all are in flight together; a tile's loads can
+// be issued before the previous tile is labelled.
+struct RawSeg {
+    float4 q[4];
+    uint32_t cls;
+    int nq;  // float path: whole quads of the row from this segment on
+};
+
+template <int T>
+__device__ __forceinline__ RawSeg load_raw(const HystArgs& a, const TileGeom& g) {
+    using TL = Tile<T>;
+    const int t = threadIdx.x;
+    const int r = t / TL::kTPR;
+    const int cb = (t % TL::kTPR) * TL::kPPT;
+    RawSeg raw;
+    raw.cls = 0;
+    raw.nq = 0;
+    if (r >= g.th) return raw;
+    if (a.smag) {
+        raw.nq = (int)min((int64_t)4, max((int64_t)0, (a.spitch - (g.X0 + cb)) >> 2));
+        if (raw.nq > 0) {
+            const float* row = a.smag + (int64_t)(g.Y0 + r) * a.spitch + g.X0 + cb;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) v[q] = reinterpret_cast<const float4*>(row)[min(q, nquads - 1)];
-    uint32_t codes = 0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const float e[4] = {v[q].x, v[q].y, v[q].z, v[q].w};
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const uint32_t c = e[k] > 0.0f ? (e[k] > hi ? 2u : (e[k] >= lo ? 1u : 0u)) : 0u;
-            codes |= (q < nquads ? c : 0u) << (2 * (4 * q + k));
+            for (int q = 0; q < 4; ++q) raw.q[q] = reinterpret_cast<const float4*>(row)[min(q, raw.nq - 1)];
+        }
+    } else {
+        const uint8_t* row = a.cls + (int64_t)(g.Y0 + r) * a.cpitch + ((g.X0 + cb) >> 2);
+        const int avail = (int)(a.cpitch - ((g.X0 + cb) >> 2));  // bytes left in the row
+        if (avail >= 4) {
+            raw.cls = *reinterpret_cast<const uint32_t*>(row);
+        } else {
+            for (int k = 0; k < avail; ++k) raw.cls |= (uint32_t)row[k] << (8 * k);
         }
     }
+    return raw;
+}
+
+// Class codes (2 bits per pixel, pixel k at bits 2k) of the thread's 16
+// pixels; on the float path from the signed strength map: kept (value > 0)
+// and > hi -> 2, kept and >= lo -> 1.  Pixels past the image edge are 0.
+template <int T>
+__device__ __forceinline__ uint32_t raw_codes(const HystArgs& a, const TileGeom& g, const RawSeg& raw) {
+    using TL = Tile<T>;
+    const int t = threadIdx.x;
+    const int r = t / TL::kTPR;
+    const int cb = (t % TL::kTPR) * TL::kPPT;
+    if (r >= g.th) return 0u;
+    uint32_t codes = raw.cls;
+    if (a.smag) {
+        const float mx = __uint_as_float(*a.maxbits);
+        const float lo = a.relative ? a.low * mx : a.low;
+        const float hi = a.relative ? a.high * mx : a.high;
+        codes = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float e[4] = {raw.q[q].x, raw.q[q].y, raw.q[q].z, raw.q[q].w};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t c = e[k] > 0.0f ? (e[k] > hi ? 2u : (e[k] >= lo ? 1u : 0u)) : 0u;
+                codes |= (q < raw.nq ? c : 0u) << (2 * (4 * q + k));
+            }
+        }
+    }
+    const int valid = min(max(a.W - (g.X0 + cb), 0), TL::kPPT);
+    if (valid < 16) codes &= (valid == 0) ? 0u : (0xFFFFFFFFu >> (32 - 2 * valid));
     return codes;
 }
 
 template <int T>
-__device__ __forceinline__ TileLabel<T> tile_label(const HystArgs& a, const TileGeom& g, int* L,
+__device__ __forceinline__ TileLabel<T> tile_label(uint32_t codes, const TileGeom& g, int* L,
                                                    uint64_t* cm, uint64_t* smk, uint32_t* strong) {
     using TL = Tile<T>;
     static_assert(TL::kPPT == 16, "row masks assume 16-pixel segments");
-    const int W = a.W;
     const int t = threadIdx.x;
     const int r = t / TL::kTPR;
     const int seg = t % TL::kTPR;
     const int cb = seg * TL::kPPT;
-    uint32_t codes = 0;
-    if (r < g.th) {
-        if (a.smag) {
-            const float mx = __uint_as_float(*a.maxbits);
-            const float lo = a.relative ? a.low * mx : a.low;
-            const float hi = a.relative ? a.high * mx : a.high;
-            // whole quads that the row pitch holds from this segment on
-            const int nq = (int)min((int64_t)4, max((int64_t)0, (a.spitch - (g.X0 + cb)) >> 2));
-            if (nq > 0)
-                codes = codes_from_signed(a.smag + (int64_t)(g.Y0 + r) * a.spitch + g.X0 + cb, nq, lo, hi);
-        } else {
-            const uint8_t* row = a.cls + (int64_t)(g.Y0 + r) * a.cpitch + ((g.X0 + cb) >> 2);
-            const int avail = (int)(a.cpitch - ((g.X0 + cb) >> 2));  // bytes left in the row
-            if (avail >= 4) {
-                codes = *reinterpret_cast<const uint32_t*>(row);
-            } else {
-                for (int k = 0; k < avail; ++k) codes |= (uint32_t)row[k] << (8 * k);
-            }
-        }
-        // pixels past the image edge are not candidates
-        const int valid = min(max(W - (g.X0 + cb), 0), TL::kPPT);
-        if (valid < 16) codes &= (valid == 0) ? 0u : (0xFFFFFFFFu >> (32 - 2 * valid));
-    }
     TileLabel<T> st;
     st.cand = compress2(codes | (codes >> 1));
     st.strong = compress2((codes >> 1) & ~codes);  // code 2
@@ -426,18 +452,17 @@ __device__ __forceinline__ Seg16 load_seg(const uint8_t* src, int valid, int vec
 
 // Pass 1 on one tile (the whole workgroup takes part).
 template <int T>
-__device__ __forceinline__ void local_tile(const HystArgs& a, int tile, int tiles_x, int vec16,
-                                           LocalSmem<T>& sm) {
+__device__ __forceinline__ void local_tile(const HystArgs& a, const TileGeom& g, const RawSeg& raw,
+                                           int vec16, LocalSmem<T>& sm) {
     using TL = Tile<T>;
     static_assert(T <= kHystCols, "border pixel indices assume T <= 64");
     int* L = sm.L;
     int* bl = sm.bl;
-    const TileGeom g = tile_geom<T>(tile, tiles_x, a.H, a.W);
     const int t = threadIdx.x;
     for (int s = t; s < TL::kPerim; s += kWGThreads) bl[s] = -1;  // "no candidate"
     for (int w = t; w < TL::kPx / 32; w += kWGThreads) sm.strong[w] = 0u;
-    if (a.max_out && tile == 0 && t == 0) *a.max_out = __uint_as_float(*a.maxbits);
-    const TileLabel<T> st = tile_label<T>(a, g, L, sm.cm, sm.smk, sm.strong);
+    if (a.max_out && g.tile == 0 && t == 0) *a.max_out = __uint_as_float(*a.maxbits);
+    const TileLabel<T> st = tile_label<T>(raw_codes<T>(a, g, raw), g, L, sm.cm, sm.smk, sm.strong);
     const int r = t / TL::kTPR;
     const int cb = (t % TL::kTPR) * TL::kPPT;
     const int me = r * kHystCols;
@@ -479,12 +504,17 @@ __device__ __forceinline__ void local_tile(const HystArgs& a, int tile, int tile
     for (int s = t; s < TL::kPerim; s += kWGThreads) a.blab[base + s] = bl[s];
 }
 
+// One tile per workgroup.  (Two adjacent tiles per workgroup, the second
+// one's loads issued before the first is labelled, measured slower: 44 -> 57
+// us for the float 4096^2 pass; the eight resident workgroups of a CU
+// already overlap one another's latencies.)  Each XCD takes a contiguous
+// range of tiles: neighbouring tiles share the cache lines of the class map
+// and the edge map, and each XCD has its own L2.
 template <int T>
 __global__ void __launch_bounds__(kWGThreads) k_hyst_local(HystArgs a, int tiles_x, int vec16) {
     __shared__ LocalSmem<T> sm;
-    // each XCD takes a contiguous range of tiles: neighbouring tiles share the
-    // cache lines of the class map and the edge map, and each XCD has its own L2
-    local_tile<T>(a, xcd_remap(blockIdx.x, gridDim.x), tiles_x, vec16, sm);
+    const TileGeom g = tile_geom<T>(xcd_remap(blockIdx.x, gridDim.x), tiles_x, a.H, a.W);
+    local_tile<T>(a, g, load_raw<T>(a, g), vec16, sm);
 }
 
 // Pass 2 for border pixel k of a tile (k < T: right edge row k; else bottom
@@ -652,7 +682,9 @@ k_hyst_local_batch(const BatchImage* imgs, const BatchDev* hdr) {
     if (task >= hdr->total_tiles) return;
     const BatchImage& im = imgs[hdr->tile_img[task]];
     const int vec16 = ((uintptr_t)im.edges % 16 == 0) && (im.epitch % 16 == 0);
-    local_tile<T>(batch_args(im, hdr->ws), task - im.tile_base, im.tiles_x, vec16, sm);
+    const HystArgs a = batch_args(im, hdr->ws);
+    const TileGeom g = tile_geom<T>(task - im.tile_base, im.tiles_x, im.H, im.W);
+    local_tile<T>(a, g, load_raw<T>(a, g), vec16, sm);
 }
 
 template <int T>
