@@ -154,7 +154,15 @@ def roofline_headline(canny, torch, bufs, H, W, steps):
             "forward_frac": round(alg / fwd_s / 1e9 / HBM_PEAK_GBS, 4),
             "valu_insts_per_launch": valu_insts,
             "valu_frac": None if valu_insts is None else
-            round(valu_insts * 64 / walk_s / VALU_PEAK_LANE_OPS, 4)}
+            round(valu_insts * 64 / walk_s / VALU_PEAK_LANE_OPS, 4),
+            # Step 4's four passes (local, merge, flags, resolve) together,
+            # on their algorithmic 0.25 B/px of class map in + 1 B/px of
+            # edges out; on this path the local pass reads the 4 B/px signed
+            # strength map instead of a class map (measured traffic in
+            # profiles/f32_4096_traffic.txt)
+            "hysteresis": {"bytes_per_launch": H * W * 1.25, "avg_us": us["hysteresis"],
+                           "achieved_gbs": round(H * W * 1.25 / (us["hysteresis"] * 1e-6) / 1e9, 1),
+                           "frac": round(H * W * 1.25 / (us["hysteresis"] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}}
 
 
 def bench_u8(canny, torch, img, steps, warmup, label):

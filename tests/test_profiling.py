@@ -80,3 +80,27 @@ def test_counters_table(tmp_path, capsys):
     assert lines[0] == ["kernel", "SQ_WAIT_ANY", "SQ_WAVES"]
     assert lines[1] == ["k_a", "9", "5"]
     assert lines[2] == ["k_b", "-", "1"]
+
+
+def test_traffic_table_uses_the_largest_copy(tmp_path, capsys):
+    """Several kernels of one run pair; the calibration is the largest copy of
+    the run (a small upload copy in the same run must not be taken for it)."""
+    copy = 256 << 20
+    fd, wd = str(tmp_path / "f"), str(tmp_path / "w")
+    write_counters(fd, [["__amd_rocclr_copyBuffer", "FETCH_SIZE", 4.0],
+                        ["__amd_rocclr_copyBuffer", "FETCH_SIZE", copy / 2048],
+                        ["__amd_rocclr_copyBuffer", "FETCH_SIZE", 3.0],
+                        ["k_a, b<1, 2>(x)", "FETCH_SIZE", 10000.0],
+                        ["k_c(y)", "FETCH_SIZE", 1.0]])
+    write_counters(wd, [["__amd_rocclr_copyBuffer", "WRITE_SIZE", copy / 1024],
+                        ["__amd_rocclr_copyBuffer", "WRITE_SIZE", 2.0],
+                        ["k_a, b<1, 2>(x)", "WRITE_SIZE", 5000.0],
+                        ["k_c(y)", "WRITE_SIZE", 1.0]])
+    profiling.main(["traffic-table", fd, wd, "--copy-bytes", str(copy),
+                    "--kernel", "k_a, b<1, 2>=25600000", "--kernel", "k_c=0"])
+    rows = [ln for ln in capsys.readouterr().out.splitlines() if not ln.startswith("#")]
+    assert rows[0].split()[0] == "kernel"
+    a = rows[1].split()
+    # fetch 2 x 10000 KiB, write 5000 KiB: 20.48 + 5.12 MB against 25.6 MB
+    assert a[-5:] == ["20.5", "5.1", "25.6", "25.6", "1.00"]
+    assert rows[2].split()[-1] == "-"
