@@ -666,7 +666,7 @@ __device__ __forceinline__ HystArgs batch_args(const BatchImage& im, char* ws) {
     a.epitch = im.epitch;
     a.blab = reinterpret_cast<int32_t*>(ws + im.blab_off);
     a.parent = reinterpret_cast<int32_t*>(ws + im.parent_off);
-    a.flag = reinterpret_cast<int32_t*>(ws + im.flag_off);
+    a.flag = reinterpret_cast<uint8_t*>(ws + im.flag_off);
     a.pmask = reinterpret_cast<uint64_t*>(ws + im.pmask_off);
     return a;
 }
@@ -739,13 +739,14 @@ static int perim(int tile_rows) { return 2 * kHystCols + 2 * tile_rows; }
 
 static size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-// blab: int32 per border slot; parent, flag: int32 per component name (256
-// per tile; only the names of this call's border components are written and
-// read); pmask: one 64-bit word per wave of a tile.  About 0.76 B per pixel.
+// blab: int32 per border slot; parent: int32 and flag: one byte per
+// component name (256 per tile; only the names of this call's border
+// components are written and read); pmask: one 64-bit word per wave of a
+// tile.  About 0.57 B per pixel.
 size_t hyst_workspace_bytes(int H, int W, int tile_rows) {
     const size_t ntiles = (size_t)ceil_div(W, kHystCols) * ceil_div(H, tile_rows);
     const size_t nnames = ntiles * (size_t)kNamesPerTile;
-    return al256(ntiles * perim(tile_rows) * 4) + 2 * al256(nnames * 4) +
+    return al256(ntiles * perim(tile_rows) * 4) + al256(nnames * 4) + al256(nnames) +
            al256(ntiles * (kWGThreads / kWave) * 8);
 }
 
@@ -757,8 +758,8 @@ void hyst_carve(void* ws, int H, int W, int tile_rows, HystArgs& a) {
     p += al256(ntiles * perim(tile_rows) * 4);
     a.parent = reinterpret_cast<int32_t*>(p);
     p += al256(nnames * 4);
-    a.flag = reinterpret_cast<int32_t*>(p);
-    p += al256(nnames * 4);
+    a.flag = reinterpret_cast<uint8_t*>(p);
+    p += al256(nnames);
     a.pmask = reinterpret_cast<uint64_t*>(p);
 }
 

@@ -95,7 +95,7 @@ struct HystArgs {
     int64_t epitch;
     int32_t* blab;    // [ntiles * perim] global component name of each border pixel
     int32_t* parent;  // [ntiles * 256] union-find forest over component names (tile * 256 + border index)
-    int32_t* flag;    // [ntiles * 256] strong flags of the names
+    uint8_t* flag;    // [ntiles * 256] strong flags of the names (1 byte each)
     uint64_t* pmask;  // [ntiles * 4] per wave of a tile: which thread segments hold pending codes
 };
 int hyst_tile_rows_default();
