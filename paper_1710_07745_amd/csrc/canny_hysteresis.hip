@@ -114,6 +114,7 @@ __device__ __forceinline__ void g_union(int* parent, int a, int b) {
 
 struct TileGeom {
     int tile, ty, tx, X0, Y0, th, tw;
+    int t;  // this thread's index in the workgroup
 };
 
 template <int T>
@@ -126,6 +127,7 @@ __device__ __forceinline__ TileGeom tile_geom(int tile, int tiles_x, int H, int 
     g.Y0 = g.ty * T;
     g.th = min(T, H - g.Y0);
     g.tw = min(kHystCols, W - g.X0);
+    g.t = threadIdx.x;
     return g;
 }
 
@@ -173,19 +175,6 @@ __device__ __forceinline__ int run_border_max(int r, int c0, int c1, int th, int
     return -1;
 }
 
-// Load this thread's class codes and label the tile's candidates in LDS.
-// Afterwards L[r*64 + s] holds the root (smallest index) of the component
-// of the run that starts at column s of row r (only run starts carry
-// entries), every root's entry carries its component's largest border index
-// and `strong` its strong bit.  cm and smk hold the 64-bit candidate and
-// strong masks of every tile row.
-//   phase 1: codes, row masks, and each run start's L entry (a run's start
-//            needs only the pixel before this thread's segment, a lane away)
-//   phase 2: the unions with the row above
-//   phase 3: each run start walks to its root and stores it; a run with a
-//            strong pixel sets its root's strong bit, and a run on the tile
-//            border raises its root's border index -- per run, from the
-//            run's extent, instead of per pixel
 // A thread's 16 pixels as loaded, before classification: four quads of the
 // signed strength map (float path) or one dword of the class map.  The
 // loads are unconditional inside the row (quads past nq re-read the last one
@@ -200,7 +189,7 @@ struct RawSeg {
 template <int T>
 __device__ __forceinline__ RawSeg load_raw(const HystArgs& a, const TileGeom& g) {
     using TL = Tile<T>;
-    const int t = threadIdx.x;
+    const int t = g.t;
     const int r = t / TL::kTPR;
     const int cb = (t % TL::kTPR) * TL::kPPT;
     RawSeg raw;
@@ -232,7 +221,7 @@ __device__ __forceinline__ RawSeg load_raw(const HystArgs& a, const TileGeom& g)
 template <int T>
 __device__ __forceinline__ uint32_t raw_codes(const HystArgs& a, const TileGeom& g, const RawSeg& raw) {
     using TL = Tile<T>;
-    const int t = threadIdx.x;
+    const int t = g.t;
     const int r = t / TL::kTPR;
     const int cb = (t % TL::kTPR) * TL::kPPT;
     if (r >= g.th) return 0u;
@@ -257,53 +246,146 @@ __device__ __forceinline__ uint32_t raw_codes(const HystArgs& a, const TileGeom&
     return codes;
 }
 
+// Inclusive prefix sum over the 64 lanes of a wave: DPP row shifts within
+// each 16-lane row, then lane 15's and lane 31's sums broadcast into the rows
+// after them.
+__device__ __forceinline__ int wave_incl_sum(int v) {
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xF, 0xF, false);  // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xF, 0xF, false);  // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, false);  // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, false);  // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false);  // row_bcast:15 -> rows 1, 3
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xC, 0xF, false);  // row_bcast:31 -> rows 2, 3
+    return v;
+}
+
+// Orders a wave's LDS writes before its later LDS reads (a wave's LDS
+// instructions execute in order; this keeps the compiler from moving them).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Runs the items of a wave's lanes (lane l's items: the set bits of its w,
+// item(bit) encoding each) spread over all 64 lanes.  In rounds of up to 64
+// items the owners write their items to the wave's list in LDS and lane j
+// runs item j of the round, so a wave takes (its item count / 64) rounds
+// instead of the largest count of one lane.
+template <typename Item, typename Work>
+__device__ __forceinline__ void wave_spread(int lane, uint64_t w, uint32_t* list, Item item, Work work) {
+    const int cnt = __popcll(w);
+    const int incl = wave_incl_sum(cnt);
+    const int total = __builtin_amdgcn_readlane(incl, kWave - 1);
+    int idx = incl - cnt;  // this lane's first item
+    for (int base = 0; base < total; base += kWave) {
+        for (; w && idx < base + kWave; w &= w - 1, ++idx) list[idx - base] = item(__ffsll((long long)w) - 1);
+        wave_lds_sync();
+        if (lane < total - base) work(list[lane]);
+        wave_lds_sync();
+    }
+}
+
+// Columns 8-adjacent to the run of row mask m that starts at column c0:
+// c0 - 1 .. c1 + 1, clipped to the row (c1 the run's last column).
+__device__ __forceinline__ uint64_t adj_window(uint64_t m, int c0) {
+    const uint64_t rest = ~m >> c0;
+    const int c1 = c0 + (rest ? __ffsll((long long)rest) - 1 : 64 - c0) - 1;
+    const uint64_t lo = c0 == 0 ? ~0ull : ~0ull << (c0 - 1);
+    const uint64_t hi = c1 >= 62 ? ~0ull : (2ull << (c1 + 1)) - 1ull;
+    return lo & hi;
+}
+
+__device__ __forceinline__ int ctz64(uint64_t v) { return __ffsll((long long)v) - 1; }
+
+// Load this thread's class codes and label the tile's candidates in LDS.
+// Afterwards L[r*64 + s] holds the root (smallest index) of the component
+// of the run that starts at column s of row r (only run starts' entries are
+// used), every root's entry carries its component's largest border index
+// and `strong` its strong bit.  cm and smk hold the 64-bit candidate and
+// strong masks of every tile row.
+//   phase 1: codes, row masks, L[i] = i for every pixel of the segment
+//   phase 2: each run start with a run of the row above among its
+//            8-neighbours points at one of them (the one holding the lowest
+//            such column): a plain store, one writer per entry.  The runs
+//            now form trees that follow the image upwards, as deep as the
+//            tile is tall.
+//   phase 3: pointer jumping flattens the trees (each linked run start
+//            repeatedly takes its parent's parent, all at once, so depths
+//            halve per step), then the run's other neighbour runs above are
+//            joined by union-find -- only rows where two branches meet.
+//   phase 4: each run start walks to its root and stores it; a run with a
+//            strong pixel sets its root's strong bit, and a run on the tile
+//            border raises its root's border index -- per run, from the
+//            run's extent, instead of per pixel
+// Phases 3 and 4 spread their run starts over the lanes of the wave
+// (wave_spread): a segment holds 0 to 8 of them, so per lane the counts are
+// uneven while a wave's total is small.
 template <int T>
 __device__ __forceinline__ TileLabel<T> tile_label(uint32_t codes, const TileGeom& g, int* L,
-                                                   uint64_t* cm, uint64_t* smk, uint32_t* strong) {
+                                                   uint64_t* cm, uint64_t* smk, uint32_t* strong,
+                                                   uint32_t* list) {
     using TL = Tile<T>;
     static_assert(TL::kPPT == 16, "row masks assume 16-pixel segments");
-    const int t = threadIdx.x;
+    const int t = g.t;
     const int r = t / TL::kTPR;
     const int seg = t % TL::kTPR;
     const int cb = seg * TL::kPPT;
+    const int me = r * kHystCols;
+    const int up = me - kHystCols;
     TileLabel<T> st;
     st.cand = compress2(codes | (codes >> 1));
     st.strong = compress2((codes >> 1) & ~codes);  // code 2
     reinterpret_cast<uint16_t*>(cm)[r * 4 + seg] = (uint16_t)st.cand;
     reinterpret_cast<uint16_t*>(smk)[r * 4 + seg] = (uint16_t)st.strong;
-    // run starts of this segment: the pixel before it is the top bit of the
-    // previous lane's segment (same row unless this is the row's first)
-    const uint32_t left = from_left(st.cand);
-    const uint32_t before = seg == 0 ? 0u : (left >> 15) & 1u;
-    const uint32_t s16 = st.cand & ~((st.cand << 1) | before);
-    for (uint32_t b = s16; b; b &= b - 1) {
-        const int i = r * kHystCols + cb + __ffs(b) - 1;
-        L[i] = i;
+    {
+        int4* l4 = reinterpret_cast<int4*>(L + me + cb);
+        const int i0 = me + cb;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) l4[q] = make_int4(i0 + 4 * q, i0 + 4 * q + 1, i0 + 4 * q + 2, i0 + 4 * q + 3);
     }
     __syncthreads();
     st.m = cm[r];
     st.S = st.m & ~(st.m << 1);
-    const uint64_t segmask = 0xFFFFull << cb;
-    const uint64_t Smine = st.S & segmask;
-    if (r > 0 && (st.m & segmask)) {  // runs may start in an earlier segment
-        const uint64_t A = cm[r - 1];
-        const uint64_t SA = A & ~(A << 1);
-        const int up = (r - 1) * kHystCols, me = r * kHystCols;
-        // a run joins the row above through its first pixel (N, or NW and NE
-        // when N is empty) and through any later pixel whose N is empty but NE
-        // is not; every other 8-neighbour is already in one of those runs
-        for (uint64_t b = st.S & A & segmask; b; b &= b - 1) {
-            const int c = __ffsll((long long)b) - 1;
-            lds_union(L, me + c, up + run_start(SA, c));
+    const uint32_t starts = (uint32_t)(st.S >> cb) & 0xFFFFu;
+    uint64_t A = 0, SA = 0;
+    uint32_t linked = 0;  // run starts of the segment (bit k: column cb + k) that point up
+    if (r > 0) {
+        A = cm[r - 1];
+        SA = A & ~(A << 1);
+        for (uint32_t b = starts; b; b &= b - 1) {
+            const int k = __ffs(b) - 1;
+            const uint64_t ov = A & adj_window(st.m, cb + k);
+            if (ov) {
+                L[me + cb + k] = up + run_start(SA, ctz64(ov));
+                linked |= 1u << k;
+            }
         }
-        for (uint64_t b = st.S & ~A & (A << 1) & segmask; b; b &= b - 1) {
-            const int c = __ffsll((long long)b) - 1;
-            lds_union(L, me + run_start(st.S, c), up + run_start(SA, c - 1));
-        }
-        for (uint64_t b = st.m & ~A & (A >> 1) & segmask; b; b &= b - 1) {
-            const int c = __ffsll((long long)b) - 1;
-            lds_union(L, me + run_start(st.S, c), up + run_start(SA, c + 1));
-        }
+    }
+    __syncthreads();
+    volatile lds_i32* V = lds_volatile(L);
+    // pointer jumping: every entry only ever moves to an ancestor (a smaller
+    // index), so a jump stays within i + 1 steps, and a concurrent union's
+    // path halving or linking leaves every pointer an ancestor as well
+    wave_spread(
+        t & (kWave - 1), linked, list, [&](int pos) -> uint32_t { return (uint32_t)(me + cb + pos); },
+        [&](uint32_t it) {
+            const int i = (int)it;
+            int x = V[i];
+            for (int steps = i; steps >= 0; --steps) {
+                const int gp = V[x];
+                if (gp == x) break;
+                x = gp;
+                V[i] = x;
+            }
+        });
+    // the run's other neighbour runs above: those starting after the run
+    // that phase 2 linked to, up to column c1 + 1
+    for (uint32_t b = linked; b; b &= b - 1) {
+        const int c0 = cb + __ffs(b) - 1;
+        const uint64_t win = adj_window(st.m, c0);
+        const int lo = ctz64(A & win);
+        for (uint64_t e = SA & win & ~((2ull << lo) - 1ull); e; e &= e - 1)
+            lds_union(L, me + c0, up + ctz64(e));
     }
     __syncthreads();
     // all unions are in: each run start walks to its root (pointers only
@@ -311,37 +393,31 @@ __device__ __forceinline__ TileLabel<T> tile_label(uint32_t codes, const TileGeo
     // ancestor), a root, or a root entry whose border bits another run has
     // already raised, hence the mask; a run start that is itself a root keeps
     // its entry (another run may be raising its border bits).
-    volatile lds_i32* V = lds_volatile(L);
-    const uint64_t srow = smk[r];
-    for (uint64_t b = Smine; b; b &= b - 1) {
-        const int c0 = __ffsll((long long)b) - 1;
-        const int i = r * kHystCols + c0;
-        int x = V[i] & kRootMask;
-        for (int steps = i; steps >= 0; --steps) {
-            const int p = V[x] & kRootMask;
-            if (p == x) break;
-            x = p;
-        }
-        if (x != i) V[i] = x;
-        // the run covers columns c0 .. c1 (its first 0 bit above c0, minus one)
-        const uint64_t rest = ~st.m >> c0;
-        const int c1 = c0 + (rest ? __ffsll((long long)rest) - 1 : 64 - c0) - 1;
-        const uint64_t span = (c1 - c0 >= 63) ? ~0ull : (((2ull << (c1 - c0)) - 1ull) << c0);
-        if (srow & span) atomicOr(&strong[x >> 5], 1u << (x & 31));
-        const int bmax = run_border_max(r, c0, c1, g.th, g.tw);
-        if (bmax >= 0) atomicMax(&L[x], x | ((1 + bmax) << kBrepShift));
-    }
+    const int th = g.th, tw = g.tw;
+    wave_spread(
+        t & (kWave - 1), starts, list, [&](int pos) -> uint32_t { return (uint32_t)(me + cb + pos); },
+        [&](uint32_t it) {
+            const int i = (int)it;
+            const int rr = i >> 6, c0 = i & (kHystCols - 1);
+            const uint64_t mrow = cm[rr];
+            const uint64_t srow = smk[rr];
+            int x = V[i] & kRootMask;
+            for (int steps = i; steps >= 0; --steps) {
+                const int p = V[x] & kRootMask;
+                if (p == x) break;
+                x = p;
+            }
+            if (x != i) V[i] = x;
+            // the run covers columns c0 .. c1 (its first 0 bit above c0, minus one)
+            const uint64_t rest = ~mrow >> c0;
+            const int c1 = c0 + (rest ? __ffsll((long long)rest) - 1 : 64 - c0) - 1;
+            const uint64_t span = (c1 - c0 >= 63) ? ~0ull : (((2ull << (c1 - c0)) - 1ull) << c0);
+            if (srow & span) atomicOr(&strong[x >> 5], 1u << (x & 31));
+            const int bmax = run_border_max(rr, c0, c1, th, tw);
+            if (bmax >= 0) atomicMax(&L[x], x | ((1 + bmax) << kBrepShift));
+        });
     __syncthreads();
     return st;
-}
-
-// Visit the border slots of pixel (r, c) of a tile clipped to th x tw.
-template <int T, typename F>
-__device__ __forceinline__ void for_slots(int r, int c, int th, int tw, F f) {
-    if (r == 0) f(c);
-    if (r == th - 1) f(kHystCols + c);
-    if (c == 0) f(2 * kHystCols + r);
-    if (c == tw - 1) f(2 * kHystCols + T + r);
 }
 
 // global names of border components: tile * kNamesPerTile + border index
@@ -349,11 +425,11 @@ constexpr int kNamesPerTile = 256;
 
 template <int T>
 struct LocalSmem {
-    int L[Tile<T>::kPx];
-    uint64_t cm[T];                  // candidate mask of each tile row
-    uint64_t smk[T];                 // strong mask of each tile row
+    alignas(16) int L[Tile<T>::kPx];
+    uint64_t cm[T];                      // candidate mask of each tile row
+    uint64_t smk[T];                     // strong mask of each tile row
     uint32_t strong[Tile<T>::kPx / 32];  // strong bit of each root
-    int bl[Tile<T>::kPerim];         // staged border names: one global store per slot
+    uint32_t list[kWGThreads];           // per wave: the items of a wave_spread round
 };
 
 // border pixel index b of tile pixel (r, c), or -1 inside (see the file comment)
@@ -457,59 +533,79 @@ __device__ __forceinline__ void local_tile(const HystArgs& a, const TileGeom& g,
     using TL = Tile<T>;
     static_assert(T <= kHystCols, "border pixel indices assume T <= 64");
     int* L = sm.L;
-    int* bl = sm.bl;
-    const int t = threadIdx.x;
-    for (int s = t; s < TL::kPerim; s += kWGThreads) bl[s] = -1;  // "no candidate"
+    const int t = g.t;
     for (int w = t; w < TL::kPx / 32; w += kWGThreads) sm.strong[w] = 0u;
     if (a.max_out && g.tile == 0 && t == 0) *a.max_out = __uint_as_float(*a.maxbits);
-    const TileLabel<T> st = tile_label<T>(raw_codes<T>(a, g, raw), g, L, sm.cm, sm.smk, sm.strong);
+    const TileLabel<T> st = tile_label<T>(raw_codes<T>(a, g, raw), g, L, sm.cm, sm.smk, sm.strong,
+                                          sm.list + (t / kWave) * kWave);
     const int r = t / TL::kTPR;
     const int cb = (t % TL::kTPR) * TL::kPPT;
     const int me = r * kHystCols;
     // every candidate: 255 / 0 for a component inside the tile (by its strong
     // bit), the pending code 1 + b for one that touches the border (b its
-    // largest border index); border pixels also stage the component's global
-    // name, and the one at index b starts its union-find entry
-    const bool border_seg = r == 0 || r == g.th - 1 || cb == 0 || cb + TL::kPPT >= g.tw;
+    // largest border index); one lookup per run that covers pixels of the
+    // segment (the first may start in an earlier segment)
     bool pending = false;
     if (r < g.th) {
-        Seg16 out;
-        const int nbase = g.tile * kNamesPerTile;
-        for (uint32_t b = st.cand; b; b &= b - 1) {
-            const int k = __ffs(b) - 1;
-            const int root = L[me + run_start(st.S, cb + k)] & kRootMask;
+        uint32_t w[4] = {0u, 0u, 0u, 0u};
+        const uint32_t starts = (uint32_t)(st.S >> cb) & 0xFFFFu;
+        for (uint32_t h = starts | (st.cand & 1u); h; h &= h - 1) {
+            const int k0 = __ffs(h) - 1;
+            const int k1 = k0 + __ffs(~st.cand >> k0) - 2;  // the run's last pixel in the segment
+            const int s0 = (starts >> k0) & 1u ? cb + k0 : run_start(st.S, cb);
+            const int root = L[me + s0] & kRootMask;
             const uint32_t br = (uint32_t)L[root] >> kBrepShift;
             const bool strong = (sm.strong[root >> 5] >> (root & 31)) & 1u;
             pending |= br != 0;
-            out.set(k, br ? br : (strong ? 255u : 0u));
-            if (border_seg && br) {
-                const int bi = border_index(r, cb + k, g.th, g.tw);
-                if (bi < 0) continue;
-                const int name = nbase + (int)br - 1;
-                for_slots<T>(r, cb + k, g.th, g.tw, [&](int s) { bl[s] = name; });
-                if (bi == (int)br - 1) {
-                    a.parent[name] = name;
-                    a.flag[name] = strong ? 1 : 0;
-                }
-            }
+            const uint32_t v = (br ? br : (strong ? 255u : 0u)) * 0x01010101u;
+            const uint32_t span = ((2u << k1) - 1u) & ~((1u << k0) - 1u);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)  // bit j of a nibble -> byte j (0x00 / 0xFF)
+                w[q] |= ((((span >> (4 * q)) & 15u) * 0x00204081u) & 0x01010101u) * 0xFFu & v;
         }
+        Seg16 out;
+        out.lo = w[0] | (uint64_t)w[1] << 32;
+        out.hi = w[2] | (uint64_t)w[3] << 32;
         const int valid = min(a.W - (g.X0 + cb), TL::kPPT);
         if (valid > 0) store_seg(a.edges + (int64_t)(g.Y0 + r) * a.epitch + g.X0 + cb, out, valid, vec16);
     }
     // one bit per thread segment with pending codes, one word per wave
     const uint64_t pm = __ballot(pending);
     if ((t & (kWave - 1)) == 0) a.pmask[(int64_t)g.tile * (kWGThreads / kWave) + t / kWave] = pm;
-    __syncthreads();  // every border slot's name is in bl
+    // the global name of every border slot's component (-1: no candidate);
+    // the slot of the pixel whose border index names the component starts its
+    // union-find entry
     const int base = g.tile * TL::kPerim;
-    for (int s = t; s < TL::kPerim; s += kWGThreads) a.blab[base + s] = bl[s];
+    for (int s = t; s < TL::kPerim; s += kWGThreads) {
+        int pr, pc;
+        bool in;
+        if (s < kHystCols) { pr = 0; pc = s; in = pc < g.tw; }
+        else if (s < 2 * kHystCols) { pr = g.th - 1; pc = s - kHystCols; in = pc < g.tw; }
+        else if (s < 2 * kHystCols + T) { pr = s - 2 * kHystCols; pc = 0; in = pr < g.th; }
+        else { pr = s - 2 * kHystCols - T; pc = g.tw - 1; in = pr < g.th; }
+        int name = -1;
+        const uint64_t mr = in ? sm.cm[pr] : 0ull;
+        if ((mr >> pc) & 1ull) {
+            const int root = L[pr * kHystCols + run_start(mr & ~(mr << 1), pc)] & kRootMask;
+            const int br = (int)((uint32_t)L[root] >> kBrepShift);  // >= 1 on the border
+            name = g.tile * kNamesPerTile + br - 1;
+            const int bi = border_index(pr, pc, g.th, g.tw);
+            if (bi == br - 1 && border_slot<T>(bi) == s) {
+                a.parent[name] = name;
+                a.flag[name] = (sm.strong[root >> 5] >> (root & 31)) & 1u;
+            }
+        }
+        a.blab[base + s] = name;
+    }
 }
 
-// One tile per workgroup.  (Two adjacent tiles per workgroup, the second
-// one's loads issued before the first is labelled, measured slower: 44 -> 57
-// us for the float 4096^2 pass; the eight resident workgroups of a CU
-// already overlap one another's latencies.)  Each XCD takes a contiguous
-// range of tiles: neighbouring tiles share the cache lines of the class map
-// and the edge map, and each XCD has its own L2.
+// One tile per workgroup.  Each XCD takes a contiguous range of tiles:
+// neighbouring tiles share the cache lines of the class map and the edge map,
+// and each XCD has its own L2.  (Persistent forms -- as many workgroups as
+// the chip holds, each taking tile after tile, from per-XCD atomic counters
+// or in a fixed order -- measured slower: 65.9 and 61.7 against 55 us for the
+// four integer passes at 4096^2; so did static pairs of tiles per workgroup
+// with the second one's loads issued early, 44 -> 57 us for the float pass.)
 template <int T>
 __global__ void __launch_bounds__(kWGThreads) k_hyst_local(HystArgs a, int tiles_x, int vec16) {
     __shared__ LocalSmem<T> sm;
