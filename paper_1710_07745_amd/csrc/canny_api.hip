@@ -213,8 +213,10 @@ int canny_hysteresis(const uint8_t* class2, int H, int W, uint8_t* edges, int64_
 }
 
 static int64_t smag_pitch(int W) { return ((int64_t)W + 3) & ~(int64_t)3; }
-// float workspace: largest-strength word, then the min/max partials
-static constexpr size_t kF32Header = 256;  // the largest-strength word
+// float workspace header: the largest-strength word (256 bytes), then the
+// walk's per-wave largest-strength slots
+static constexpr size_t kF32SlotsOff = 256;
+static constexpr size_t kF32Header = kF32SlotsOff + align256(4 * (size_t)kMaxSlots);
 
 size_t canny_f32_workspace_bytes(int H, int W) {
     if (!size_ok(H, W)) return 0;
@@ -275,6 +277,11 @@ static int f32_impl(const float* in, int64_t in_pitch, int H, int W, float sigma
     const bool fused = f.smag && !class2 && !mag_out && edges;
     f.skip_classify = fused ? 1 : 0;
     f.sector = sector;
+    // Fused: the walk leaves one largest-strength slot per wave and every
+    // hysteresis workgroup reduces them, so no launch has to clear a shared
+    // word first (up to kMaxSlots waves; larger images keep the word).
+    const int nslots = fused ? f32_walk_waves(f) : 0;
+    if (nslots > 0 && nslots <= kMaxSlots) f.maxslots = reinterpret_cast<uint32_t*>(w + kF32SlotsOff);
     hipError_t e = launch_f32_forward(f, s);
     if (e != hipSuccess || !edges) return status_of(e);
     HystArgs h;
@@ -284,6 +291,8 @@ static int f32_impl(const float* in, int64_t in_pitch, int H, int W, float sigma
         h.smag = f.smag;
         h.spitch = f.spitch;
         h.maxbits = f.maxbits;
+        h.maxslots = f.maxslots;
+        h.nslots = f.maxslots ? nslots : 0;
         h.low = low;
         h.high = high;
         h.relative = f.relative;

@@ -21,7 +21,11 @@
 // largest M into one word (atomicMax on the float bits, order-independent
 // because the value is non-negative), then an elementwise pass that derives
 // the thresholds from that word and writes the class map.  The walk, the
-// expensive part, therefore runs once per image in both cases.
+// expensive part, therefore runs once per image in both cases.  When only
+// edges are asked for, the hysteresis pass classifies from the signed map
+// itself; then each wave stores its largest M in a slot of its own and every
+// hysteresis workgroup reduces the slots, so nothing has to clear a shared
+// word before the walk (no extra launch).
 //
 // Accuracy: every stage before the strength is linear, so the walk filters
 // X - off(x) instead of X, with off a line in the column, c + a x', taken
@@ -163,8 +167,9 @@ __device__ __forceinline__ OffsetLine offset_line(const F4& r0, int lane) {
     return ol;
 }
 
+// Returns the wave's largest M as float bits (0 unless SIGNED), in every lane.
 template <int R, int RR, bool SIGNED, bool SECTOR, bool EDGE>
-__device__ __forceinline__ void f32_walk(const F32FwdArgs& a, int X0, int Y0, int lane, int fast_ok) {
+__device__ __forceinline__ uint32_t f32_walk(const F32FwdArgs& a, int X0, int Y0, int lane, int fast_ok) {
     static_assert(!(SIGNED && SECTOR), "the four-sector variant classifies in the walk");
     constexpr int HL = WalkShape<R>::HL;
     constexpr int HR = WalkShape<R>::HR;
@@ -418,9 +423,19 @@ __device__ __forceinline__ void f32_walk(const F32FwdArgs& a, int X0, int Y0, in
         }
     }
 
-    if (SIGNED) {
-        const uint32_t v = bc<uint32_t>(wave_max(out_lane ? mmax : 0.0f));
-        if (lane == 0 && v) atomicMax(a.maxbits, v);
+    return SIGNED ? bc<uint32_t>(wave_max(out_lane ? mmax : 0.0f)) : 0u;
+}
+
+// A wave's largest M: into its own slot when the consumer reduces the slots
+// (every wave of the launch stores one, zeros included), else into the
+// shared word (atomicMax on non-negative float bits, order-independent).
+template <bool SIGNED>
+__device__ __forceinline__ void publish_max(const F32FwdArgs& a, int wave, int lane, uint32_t v) {
+    if (!SIGNED) return;
+    if (a.maxslots) {
+        if (lane == 0) a.maxslots[wave] = v;
+    } else if (lane == 0 && v) {
+        atomicMax(a.maxbits, v);
     }
 }
 
@@ -443,10 +458,9 @@ k_f32_forward(F32FwdArgs a, int strips_x, int nwaves, int fast_ok) {
     const int Y0 = blk * RR;
     const bool interior = fast_ok && X0 - 4 * HL >= 0 && X0 + SC + 4 * HL <= a.W &&
                           Y0 - HR >= 0 && Y0 + RR + HR <= a.H;
-    if (interior)
-        f32_walk<R, RR, SIGNED, SECTOR, false>(a, X0, Y0, lane, fast_ok);
-    else
-        f32_walk<R, RR, SIGNED, SECTOR, true>(a, X0, Y0, lane, fast_ok);
+    const uint32_t v = interior ? f32_walk<R, RR, SIGNED, SECTOR, false>(a, X0, Y0, lane, fast_ok)
+                                : f32_walk<R, RR, SIGNED, SECTOR, true>(a, X0, Y0, lane, fast_ok);
+    publish_max<SIGNED>(a, wave, lane, v);
 }
 
 // Balanced launch: interior blocks of RRI rows, border blocks of RRE rows
@@ -483,14 +497,15 @@ k_f32_forward_bal(F32FwdArgs a, WalkPlan p, int fast_ok) {
             Y0 = RRE + p.k * RRI + (blk - 1 - p.k) * RRE;
         }
     }
+    uint32_t v = 0;
     if (interior) {
-        if (!(fast_ok && X0 - 4 * HL >= 0 && X0 + SC + 4 * HL <= a.W && Y0 - HR >= 0 &&
-              Y0 + RRI + HR <= a.H))
-            return;  // unreachable for a plan from make_walk_plan
-        f32_walk<R, RRI, SIGNED, SECTOR, false>(a, X0, Y0, lane, fast_ok);
+        if (fast_ok && X0 - 4 * HL >= 0 && X0 + SC + 4 * HL <= a.W && Y0 - HR >= 0 &&
+            Y0 + RRI + HR <= a.H)  // always true for a plan from make_walk_plan
+            v = f32_walk<R, RRI, SIGNED, SECTOR, false>(a, X0, Y0, lane, fast_ok);
     } else {
-        f32_walk<R, RRE, SIGNED, SECTOR, true>(a, X0, Y0, lane, fast_ok);
+        v = f32_walk<R, RRE, SIGNED, SECTOR, true>(a, X0, Y0, lane, fast_ok);
     }
+    publish_max<SIGNED>(a, wave, lane, v);
 }
 
 constexpr int kRowThreads = 256;  // one workgroup walks whole rows
@@ -616,10 +631,24 @@ bool walk_plan_ok(const WalkPlan& p, int H, int W, int fast_ok) {
 // images (halo rows amortised) and short ones small images (more waves in
 // flight).  The balanced split unless that leaves fewer than 1024 waves (one
 // per SIMD); then 8 rows per wave.
+// interior waves may read rows as aligned 16-byte quads
+int walk_fast_ok(const F32FwdArgs& a) { return ((uintptr_t)a.in % 16 == 0) && (a.pitch % 4 == 0); }
+
+template <int R>
+bool use_balanced(const WalkPlan& p, int H, int W, int fast_ok) {
+    return p.nwaves >= 1024 && walk_plan_ok<R>(p, H, W, fast_ok);
+}
+
+template <int R>
+int walk_waves_r(int H, int W, int fast_ok) {
+    const WalkPlan p = make_walk_plan<R>(H, W, fast_ok);
+    return use_balanced<R>(p, H, W, fast_ok) ? p.nwaves : ceil_div(W, WalkShape<R>::SC) * ceil_div(H, 8);
+}
+
 template <int R, bool SIGNED, bool SECTOR = false>
 void launch_walk_sized(const F32FwdArgs& a, int fast_ok, hipStream_t s) {
     const WalkPlan p = make_walk_plan<R>(a.H, a.W, fast_ok);
-    if (p.nwaves >= 1024 && walk_plan_ok<R>(p, a.H, a.W, fast_ok)) {
+    if (use_balanced<R>(p, a.H, a.W, fast_ok)) {
         hipLaunchKernelGGL((k_f32_forward_bal<R, kRRI, kRRE, SIGNED, SECTOR>), dim3(ceil_div(p.nwaves, kWavesPerWG)),
                            dim3(kWGThreads), 0, s, a, p, fast_ok);
     } else {
@@ -629,7 +658,7 @@ void launch_walk_sized(const F32FwdArgs& a, int fast_ok, hipStream_t s) {
 
 template <int R>
 hipError_t launch_radius(const F32FwdArgs& a, hipStream_t s) {
-    const int fast_ok = ((uintptr_t)a.in % 16 == 0) && (a.pitch % 4 == 0);
+    const int fast_ok = walk_fast_ok(a);
     if (!a.smag) {  // absolute thresholds, no max: classify in the walk
         StageTimer t(CANNY_STAGE_F32_WALK, s);
         if (a.sector)
@@ -638,7 +667,7 @@ hipError_t launch_radius(const F32FwdArgs& a, hipStream_t s) {
             launch_walk_sized<R, false, false>(a, fast_ok, s);
         return hipGetLastError();
     }
-    {
+    if (!a.maxslots) {  // per-wave slots need no clearing
         StageTimer t(CANNY_STAGE_F32_CLEAR, s);
         hipLaunchKernelGGL(k_f32_clear_max, dim3(1), dim3(kWave), 0, s, a.maxbits);
     }
@@ -654,6 +683,21 @@ hipError_t launch_radius(const F32FwdArgs& a, hipStream_t s) {
 }
 
 }  // namespace
+
+int f32_walk_waves(const F32FwdArgs& a) {
+    const int fast_ok = walk_fast_ok(a);
+    switch (a.radius) {
+        case 1: return walk_waves_r<1>(a.H, a.W, fast_ok);
+        case 2: return walk_waves_r<2>(a.H, a.W, fast_ok);
+        case 3: return walk_waves_r<3>(a.H, a.W, fast_ok);
+        case 4: return walk_waves_r<4>(a.H, a.W, fast_ok);
+        case 5: return walk_waves_r<5>(a.H, a.W, fast_ok);
+        case 6: return walk_waves_r<6>(a.H, a.W, fast_ok);
+        case 7: return walk_waves_r<7>(a.H, a.W, fast_ok);
+        case 8: return walk_waves_r<8>(a.H, a.W, fast_ok);
+        default: return 0;
+    }
+}
 
 hipError_t launch_f32_forward(const F32FwdArgs& a, hipStream_t s) {
     switch (a.radius) {

@@ -7,15 +7,14 @@
 //
 // The image is cut into 64-column x T-row tiles.  Four launches:
 //   1. local:  each workgroup labels its tile in LDS.  Candidates in a row
-//              are linked into runs first; then only the unions that can
-//              join a run to the row above are made (a run's first pixel
-//              joins N, or NW and NE when N is empty; a later pixel joins NE
-//              only when N is empty) -- the same components as joining every
-//              8-neighbour, with about one union per run instead of four per
-//              pixel.  Links use atomicMin (roots = smallest pixel index);
-//              once all unions are in, every run start finds its root with a
-//              read-only walk.  A component that does not touch the tile
-//              border is decided here: its pixels get 255 if it holds a
+//              form runs; a run is 8-connected to the runs of the row above
+//              that meet columns c0 - 1 .. c1 + 1.  Each run start first
+//              points at one of them (a plain store), pointer jumping
+//              flattens the resulting trees, and union-find (atomicMin, roots
+//              = smallest pixel index) joins the remaining pairs, which only
+//              occur where two branches meet; every run start then finds its
+//              root.  A component that does not touch the tile border is
+//              decided here: its pixels get 255 if it holds a
 //              strong pixel, else 0.  A component that touches the border is
 //              named globally by tile * 256 + b, b (0..251) the largest index
 //              of its border pixels; the pass writes, per tile-border pixel,
@@ -26,8 +25,9 @@
 //              edges unions its component with the 8-connected candidates
 //              across the edge (global union-find, atomicMin linking).
 //   3. flags:  one thread per border slot finds its component's root
-//              (read-only walk), stores it (flattening the forest) and ORs the
-//              component's strong flag into the root's.
+//              (read-only walk), stores it in the name's entry (flattening
+//              the forest) and in the slot, and ORs the component's strong
+//              flag into the root's.
 //   4. resolve: each workgroup rewrites the pending pixels of its tile to
 //              255 / 0 from the flag of the root named by the border pixel
 //              the code points at.
@@ -219,7 +219,7 @@ __device__ __forceinline__ RawSeg load_raw(const HystArgs& a, const TileGeom& g)
 // pixels; on the float path from the signed strength map: kept (value > 0)
 // and > hi -> 2, kept and >= lo -> 1.  Pixels past the image edge are 0.
 template <int T>
-__device__ __forceinline__ uint32_t raw_codes(const HystArgs& a, const TileGeom& g, const RawSeg& raw) {
+__device__ __forceinline__ uint32_t raw_codes(const HystArgs& a, const TileGeom& g, const RawSeg& raw, float mx) {
     using TL = Tile<T>;
     const int t = g.t;
     const int r = t / TL::kTPR;
@@ -227,7 +227,6 @@ __device__ __forceinline__ uint32_t raw_codes(const HystArgs& a, const TileGeom&
     if (r >= g.th) return 0u;
     uint32_t codes = raw.cls;
     if (a.smag) {
-        const float mx = __uint_as_float(*a.maxbits);
         const float lo = a.relative ? a.low * mx : a.low;
         const float hi = a.relative ? a.high * mx : a.high;
         codes = 0;
@@ -257,6 +256,17 @@ __device__ __forceinline__ int wave_incl_sum(int v) {
     v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false);  // row_bcast:15 -> rows 1, 3
     v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xC, 0xF, false);  // row_bcast:31 -> rows 2, 3
     return v;
+}
+
+// Largest value over the 64 lanes of a wave, in every lane.
+__device__ __forceinline__ uint32_t wave_umax(uint32_t v) {
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, false));  // row_shr:1
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, false));  // row_shr:2
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, false));  // row_shr:4
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, false));  // row_shr:8
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false));  // row_bcast:15
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false));  // row_bcast:31
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, kWave - 1);
 }
 
 // Orders a wave's LDS writes before its later LDS reads (a wave's LDS
@@ -349,15 +359,19 @@ __device__ __forceinline__ TileLabel<T> tile_label(uint32_t codes, const TileGeo
     const uint32_t starts = (uint32_t)(st.S >> cb) & 0xFFFFu;
     uint64_t A = 0, SA = 0;
     uint32_t linked = 0;  // run starts of the segment (bit k: column cb + k) that point up
+    uint32_t more = 0;    // ... and have more than one neighbour run above
     if (r > 0) {
         A = cm[r - 1];
         SA = A & ~(A << 1);
         for (uint32_t b = starts; b; b &= b - 1) {
             const int k = __ffs(b) - 1;
-            const uint64_t ov = A & adj_window(st.m, cb + k);
+            const uint64_t win = adj_window(st.m, cb + k);
+            const uint64_t ov = A & win;
             if (ov) {
-                L[me + cb + k] = up + run_start(SA, ctz64(ov));
+                const int lo = ctz64(ov);
+                L[me + cb + k] = up + run_start(SA, lo);
                 linked |= 1u << k;
+                if (SA & win & ~((2ull << lo) - 1ull)) more |= 1u << k;
             }
         }
     }
@@ -380,7 +394,7 @@ __device__ __forceinline__ TileLabel<T> tile_label(uint32_t codes, const TileGeo
         });
     // the run's other neighbour runs above: those starting after the run
     // that phase 2 linked to, up to column c1 + 1
-    for (uint32_t b = linked; b; b &= b - 1) {
+    for (uint32_t b = more; b; b &= b - 1) {
         const int c0 = cb + __ffs(b) - 1;
         const uint64_t win = adj_window(st.m, c0);
         const int lo = ctz64(A & win);
@@ -430,6 +444,7 @@ struct LocalSmem {
     uint64_t smk[T];                     // strong mask of each tile row
     uint32_t strong[Tile<T>::kPx / 32];  // strong bit of each root
     uint32_t list[kWGThreads];           // per wave: the items of a wave_spread round
+    uint32_t wmax[kWGThreads / kWave];   // per wave: largest strength slot seen
 };
 
 // border pixel index b of tile pixel (r, c), or -1 inside (see the file comment)
@@ -535,8 +550,37 @@ __device__ __forceinline__ void local_tile(const HystArgs& a, const TileGeom& g,
     int* L = sm.L;
     const int t = g.t;
     for (int w = t; w < TL::kPx / 32; w += kWGThreads) sm.strong[w] = 0u;
-    if (a.max_out && g.tile == 0 && t == 0) *a.max_out = __uint_as_float(*a.maxbits);
-    const TileLabel<T> st = tile_label<T>(raw_codes<T>(a, g, raw), g, L, sm.cm, sm.smk, sm.strong,
+    // the float path's largest strength: one word, or the walk's per-wave
+    // slots reduced here (non-negative float bits order as unsigned integers)
+    float mx = 0.0f;
+    if (a.smag) {
+        uint32_t mb;
+        if (a.maxslots) {
+            // 16-byte loads, all in flight at once (kMaxSlots / 4 / 256 per
+            // thread); words past nslots in the last quad are masked
+            static_assert(kMaxSlots % (4 * kWGThreads) == 0, "whole quads per thread");
+            const uint4* q4 = reinterpret_cast<const uint4*>(a.maxslots);
+            uint32_t m = 0;
+#pragma unroll
+            for (int k = 0; k < kMaxSlots / 4 / kWGThreads; ++k) {
+                const int q = t + k * kWGThreads;
+                if (4 * q < a.nslots) {
+                    const uint4 v = q4[q];
+                    const int n = a.nslots - 4 * q;  // valid words of this quad (>= 1)
+                    m = max(m, max(max(v.x, n > 1 ? v.y : 0u), max(n > 2 ? v.z : 0u, n > 3 ? v.w : 0u)));
+                }
+            }
+            m = wave_umax(m);
+            if ((t & (kWave - 1)) == 0) sm.wmax[t / kWave] = m;
+            __syncthreads();
+            mb = max(max(sm.wmax[0], sm.wmax[1]), max(sm.wmax[2], sm.wmax[3]));
+        } else {
+            mb = *a.maxbits;
+        }
+        mx = __uint_as_float(mb);
+        if (a.max_out && g.tile == 0 && t == 0) *a.max_out = mx;
+    }
+    const TileLabel<T> st = tile_label<T>(raw_codes<T>(a, g, raw, mx), g, L, sm.cm, sm.smk, sm.strong,
                                           sm.list + (t / kWave) * kWave);
     const int r = t / TL::kTPR;
     const int cb = (t % TL::kTPR) * TL::kPPT;
@@ -672,6 +716,7 @@ __device__ __forceinline__ void flags_one(const HystArgs& a, int s) {
         p = a.parent[x];
     }
     a.parent[gid] = x;
+    a.blab[s] = x;  // the slot now names the root: one load less in the resolve pass
     if (a.flag[gid]) a.flag[x] = 1;
 }
 
@@ -713,8 +758,8 @@ __device__ __forceinline__ void resolve_tile(const HystArgs& a, int tile, int ti
     }
     const int base = g.tile * TL::kPerim;
     if (t < 2 * kHystCols + 2 * (T - 2)) {
-        const int gid = a.blab[base + border_slot<T>(t)];
-        res[t] = gid >= 0 && a.flag[a.parent[gid]] ? 255 : 0;
+        const int root = a.blab[base + border_slot<T>(t)];  // the flags pass stored the root
+        res[t] = root >= 0 && a.flag[root] ? 255 : 0;
     }
     __syncthreads();
     if (!mine) return;

@@ -90,6 +90,8 @@ struct HystArgs {
     float low = 0.0f, high = 0.0f;
     int relative = 0;
     float* max_out = nullptr;
+    const uint32_t* maxslots = nullptr;  // if set: the largest strength is the max of nslots
+    int nslots = 0;                      // per-wave slots (16-byte aligned, <= kMaxSlots; maxbits unused)
     int H, W;
     uint8_t* edges;
     int64_t epitch;
@@ -120,7 +122,12 @@ struct F32FwdArgs {
     float* max_out;   // optional
     int skip_classify;  // signed path only: the hysteresis pass classifies instead
     int sector;         // one-launch path only: four-sector direction instead of interpolation
+    uint32_t* maxslots = nullptr;  // signed path: one largest-M slot per wave (no clearing) instead of maxbits
 };
+// Largest number of per-wave maximum slots the float workspace holds; the
+// hysteresis local pass reduces them in every workgroup.
+constexpr int kMaxSlots = 4096;
+int f32_walk_waves(const F32FwdArgs& a);  // waves of the walk launch for a
 // Laplacian zero-crossing detector (canny_log.hip)
 struct LogArgs {
     const uint8_t* in;
