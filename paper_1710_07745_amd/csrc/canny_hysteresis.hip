@@ -745,6 +745,12 @@ __device__ __forceinline__ void resolve_tile(const HystArgs& a, int tile, int ti
     using TL = Tile<T>;
     static_assert(kWGThreads >= 3 * kHystCols + T - 4, "one thread per border pixel index");
     const int t = threadIdx.x;
+    // the border names (roots since the flags pass) are loaded together with
+    // the pending masks, so a tile with pending segments waits for two
+    // dependent loads (masks and names, then segments and root flags), not three
+    const bool bthr = t < 2 * kHystCols + 2 * (T - 2);
+    int root = -1;
+    if (bthr) root = a.blab[(int64_t)tile * TL::kPerim + border_slot<T>(t)];
     // segments with pending codes (the local pass's masks; identical reads in
     // every thread, so the early exit below is uniform)
     const uint64_t* pmt = a.pmask + (int64_t)tile * (kWGThreads / kWave);
@@ -758,18 +764,12 @@ __device__ __forceinline__ void resolve_tile(const HystArgs& a, int tile, int ti
     const int cb = (t % TL::kTPR) * TL::kPPT;
     const int valid = r < g.th ? min(a.W - (g.X0 + cb), TL::kPPT) : 0;
     uint8_t* dst = a.edges + (int64_t)(g.Y0 + r) * a.epitch + g.X0 + cb;
-    // the segment's bytes are read first so that their latency overlaps the
-    // lookups below
     Seg16 out;
     if (mine) {
         const int col0 = g.X0 + cb;
         out = load_seg(dst, valid, vec16, col0 >= 4 && col0 + TL::kPPT + 4 <= a.W);
     }
-    const int base = g.tile * TL::kPerim;
-    if (t < 2 * kHystCols + 2 * (T - 2)) {
-        const int root = a.blab[base + border_slot<T>(t)];  // the flags pass stored the root
-        res[t] = root >= 0 && a.flag[root] ? 255 : 0;
-    }
+    if (bthr) res[t] = root >= 0 && a.flag[root] ? 255 : 0;
     __syncthreads();
     if (!mine) return;
 #pragma unroll

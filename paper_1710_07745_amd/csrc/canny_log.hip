@@ -70,13 +70,15 @@ __device__ __forceinline__ uint32_t to_left0(uint32_t v0, uint32_t v1) {
     return align16(v0, from_left(v1));
 }
 
-template <int R, bool BORDER>
-__device__ __forceinline__ void log_walk(const LogArgs& a, int X0, int Y0, int lane, bool fast_ok) {
+// E4: the edge rows take one 4-byte store per lane (4-byte aligned rows);
+// else one byte store per pixel.  LAP: the Laplacian is written too.
+template <int R, bool BORDER, bool E4, bool LAP>
+__device__ __forceinline__ void log_walk(const LogArgs& a, int X0, int Y0, int lane) {
+    static_assert(!(BORDER && E4), "border waves store bytes");
     const int H = a.H, W = a.W;
     const int c0 = X0 - 4 + 4 * lane;
 
     Border bd;
-    bool fast = true;
     if (BORDER) {
         bd.left = X0 == 0;
         bd.right = X0 + kU8StripCols + 4 > W;
@@ -89,20 +91,36 @@ __device__ __forceinline__ void log_walk(const LogArgs& a, int X0, int Y0, int l
         bd.mL1 = (c0 + 2 < 0 ? 0xFFFFu : 0u) | (c0 + 3 < 0 ? 0xFFFF0000u : 0u);
         bd.mR0 = (c0 >= W ? 0xFFFFu : 0u) | (c0 + 1 >= W ? 0xFFFF0000u : 0u);
         bd.mR1 = (c0 + 2 >= W ? 0xFFFFu : 0u) | (c0 + 3 >= W ? 0xFFFF0000u : 0u);
-        fast = fast_ok && c0 >= 0 && c0 + 4 <= W;
     }
     const i16x2 t2 = {(short)a.t, (short)a.t};
     const bool store_lane = lane >= 1 && lane <= 62 && (!BORDER || c0 < W);
-    const bool full4 = !BORDER || c0 + 4 <= W;  // all four columns inside the image
+    // Every store is issued unconditionally through a buffer descriptor; a
+    // lane or pixel that must not be written carries an offset past the
+    // range, and the hardware drops it.  With no store behind a branch the
+    // compiler knows how many memory operations are outstanding and waits
+    // only for the input row it needs, not for the prefetched ones.
+    constexpr uint32_t kDrop = 0x80000000u;
+    uint32_t boff[4], loff[4];  // byte offsets of the pixel in the edge and Laplacian rows
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const bool ok = store_lane && (!BORDER || c0 + k < W);
+        boff[k] = ok ? (uint32_t)(c0 + k) : kDrop;
+        loff[k] = ok ? 2u * (uint32_t)(c0 + k) : kDrop;
+    }
 
-    constexpr int kPF = 12;  // input rows loaded ahead of use
+    // input rows are loaded kPF rows ahead of their use; border waves hold
+    // four byte loads per row, so they look fewer rows ahead
+    constexpr int kPF = BORDER ? 6 : 12;
     auto load_row = [&](int i) -> uint32_t {
         if (BORDER) {
             const int y = min(max(Y0 - 4 + i, 0), H - 1);
-            return load_px4(a.in + (int64_t)y * a.pitch, c0, W, fast);
+            return load_px4_clamped(a.in + (int64_t)y * a.pitch, c0, W);
         }
-        const uint8_t* rowp = uniform_ptr(a.in + (int64_t)(Y0 - 4 + i) * a.pitch);
-        return *reinterpret_cast<const uint32_t*>(rowp + (uint32_t)c0);
+        // the row's base in scalar registers, the lane's offset (c0 >= 0 for
+        // interior waves) in one vector register
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<uint8_t*>(a.in + (int64_t)(Y0 - 4 + i) * a.pitch), (short)0, 0x7fffffff, 0x00020000);
+        return __builtin_amdgcn_raw_buffer_load_b32(rs, c0, 0, 0);
     };
     uint32_t q[kPF];
 #pragma unroll
@@ -171,8 +189,8 @@ __device__ __forceinline__ void log_walk(const LogArgs& a, int X0, int Y0, int l
         // vertical pair (n, n+1); the mark of (n-1, n) for row n comes from
         // the previous row's test (or, for the wave's first row, is tested
         // here).  Then the zeros between opposite neighbours.
-        const int n = g - 1;
-        if (BORDER && n >= H) continue;
+        const int n = g - 1;  // rows past the image (border waves) store nothing
+        const bool live = !BORDER || n < H;
         const Sgn c0s = sgn(S(lw0[1])), c1s = sgn(S(lw1[1]));
         const Sgn u0s = sgn(S(lw0[0])), u1s = sgn(S(lw1[0]));
         const Sgn d0s = sgn(S(lw0[2])), d1s = sgn(S(lw1[2]));
@@ -210,22 +228,24 @@ __device__ __forceinline__ void log_walk(const LogArgs& a, int X0, int Y0, int l
         m1 = full_mask(m1);
         const uint32_t c0v = lw0[1], c1v = lw1[1];
         const uint32_t bytes = perm(m1, m0, 0x07050301u);  // 0xFF / 0x00 per pixel
-        if (store_lane) {
-            uint8_t* erow = a.edges + (int64_t)n * a.epitch;
-            if (full4 && a.estore4) {
-                *reinterpret_cast<uint32_t*>(erow + c0) = bytes;
-            } else {
+        const int64_t nr = BORDER ? min(n, H - 1) : n;
+        const __amdgpu_buffer_rsrc_t er = __builtin_amdgcn_make_buffer_rsrc(
+            a.edges + nr * a.epitch, (short)0, 0x7fffffff, 0x00020000);
+        if (E4) {
+            __builtin_amdgcn_raw_buffer_store_b32(bytes, er, (int)(store_lane ? (uint32_t)c0 : kDrop), 0, 0);
+        } else {
 #pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    if (!BORDER || c0 + k < W) erow[c0 + k] = (uint8_t)(bytes >> (8 * k));
-            }
-            if (a.lap) {
-                int16_t* lrow = a.lap + (int64_t)n * a.lpitch;
-                const uint32_t lv[2] = {c0v, c1v};
+            for (int k = 0; k < 4; ++k)
+                __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(bytes >> (8 * k)), er, (int)(live ? boff[k] : kDrop), 0, 0);
+        }
+        if (LAP) {
+            const __amdgpu_buffer_rsrc_t lr = __builtin_amdgcn_make_buffer_rsrc(
+                a.lap + nr * a.lpitch, (short)0, 0x7fffffff, 0x00020000);
+            const uint32_t lv[2] = {c0v, c1v};
 #pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    if (!BORDER || c0 + k < W) lrow[c0 + k] = (int16_t)(lv[k >> 1] >> (16 * (k & 1)));
-            }
+            for (int k = 0; k < 4; ++k)
+                __builtin_amdgcn_raw_buffer_store_b16((uint16_t)(lv[k >> 1] >> (16 * (k & 1))), lr,
+                                                      (int)(live ? loff[k] : kDrop), 0, 0);
         }
     }
 }
@@ -246,8 +266,15 @@ k_log_u8(LogArgs a, int strips_x, int nwaves, int fast_ok) {
     const int Y0 = blk * R;
     const bool interior = fast_ok && X0 >= 4 && X0 + kU8StripCols + 4 <= a.W && Y0 >= 4 &&
                           Y0 + R + 4 <= a.H;
-    if (interior) log_walk<R, false>(a, X0, Y0, lane, true);
-    else log_walk<R, true>(a, X0, Y0, lane, fast_ok);
+    if (a.lap) {
+        if (interior && a.estore4) log_walk<R, false, true, true>(a, X0, Y0, lane);
+        else if (interior) log_walk<R, false, false, true>(a, X0, Y0, lane);
+        else log_walk<R, true, false, true>(a, X0, Y0, lane);
+    } else {
+        if (interior && a.estore4) log_walk<R, false, true, false>(a, X0, Y0, lane);
+        else if (interior) log_walk<R, false, false, false>(a, X0, Y0, lane);
+        else log_walk<R, true, false, false>(a, X0, Y0, lane);
+    }
 }
 
 // Balanced launch (the integer forward's split, U8Plan): border blocks of
@@ -284,9 +311,17 @@ k_log_u8_bal(LogArgs a, U8Plan p, int fast_ok) {
     if (interior) {
         if (!(fast_ok && X0 >= 4 && X0 + kU8StripCols + 4 <= a.W && Y0 >= 4 && Y0 + RRI + 4 <= a.H))
             return;  // unreachable for a plan from make_u8_plan
-        log_walk<RRI, false>(a, X0, Y0, lane, true);
+        if (a.lap) {
+            if (a.estore4) log_walk<RRI, false, true, true>(a, X0, Y0, lane);
+            else log_walk<RRI, false, false, true>(a, X0, Y0, lane);
+        } else {
+            if (a.estore4) log_walk<RRI, false, true, false>(a, X0, Y0, lane);
+            else log_walk<RRI, false, false, false>(a, X0, Y0, lane);
+        }
+    } else if (a.lap) {
+        log_walk<RRE, true, false, true>(a, X0, Y0, lane);
     } else {
-        log_walk<RRE, true>(a, X0, Y0, lane, fast_ok);
+        log_walk<RRE, true, false, false>(a, X0, Y0, lane);
     }
 }
 

@@ -52,6 +52,19 @@ __device__ __forceinline__ void fix_cols(uint32_t& p0, uint32_t& p1, const Borde
     }
 }
 
+// The lane's 4 pixels with replicated borders as four byte loads: the same
+// instructions in every lane (no branch), so the walk's load-wait counts stay
+// exact.
+__device__ __forceinline__ uint32_t load_px4_clamped(const uint8_t* row, int c0, int W) {
+    uint32_t v = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int c = min(max(c0 + k, 0), W - 1);
+        v |= (uint32_t)row[c] << (8 * k);
+    }
+    return v;
+}
+
 __device__ __forceinline__ uint32_t load_px4(const uint8_t* row, int c0, int W, bool fast) {
     if (fast) return *reinterpret_cast<const uint32_t*>(row + c0);
     uint32_t v = 0;

@@ -111,13 +111,12 @@ __device__ __forceinline__ uint32_t classify4(const MRow& Mu, const MRow& Mc, co
 // re-extension is needed.  BORDER = true: clamped loads and per-stage
 // replication of the edge row / column.
 template <int R, bool BORDER>
-__device__ __forceinline__ void walk(const U8FwdArgs& a, int X0, int Y0, int lane, bool fast_ok) {
+__device__ __forceinline__ void walk(const U8FwdArgs& a, int X0, int Y0, int lane) {
     const int H = a.H, W = a.W;
     const int c0 = X0 - 4 + 4 * lane;
 
     Border bd;
     uint32_t vmask0 = 0xFFFFFFFFu, vmask1 = 0xFFFFFFFFu;
-    bool fast = true;
     if (BORDER) {
         bd.left = X0 == 0;
         bd.right = X0 + kU8StripCols + 4 > W;
@@ -132,22 +131,30 @@ __device__ __forceinline__ void walk(const U8FwdArgs& a, int X0, int Y0, int lan
         bd.mR1 = (c0 + 2 >= W ? 0xFFFFu : 0u) | (c0 + 3 >= W ? 0xFFFF0000u : 0u);
         vmask0 = ~bd.mR0;  // output columns inside the image
         vmask1 = ~bd.mR1;
-        fast = fast_ok && c0 >= 0 && c0 + 4 <= W;
     }
     const uint32_t low2 = ((uint32_t)a.low & 0xFFFFu) * 0x10001u;
     const uint32_t high2 = ((uint32_t)a.high & 0xFFFFu) * 0x10001u;
     const bool store_lane = lane >= 1 && lane <= 62 && (!BORDER || c0 < W);
-    const uint32_t cls_off = (uint32_t)(c0 >> 2);  // only used by storing lanes (c0 >= 0)
+    // Class bytes go out through an unconditional buffer store: lanes that do
+    // not store carry an offset past the descriptor's range and the hardware
+    // drops their writes.  A store behind a branch leaves the number of
+    // outstanding memory operations unknown to the compiler, which then waits
+    // for all of them -- the prefetched input rows included.
+    const uint32_t soff = store_lane ? (uint32_t)(c0 >> 2) : 0x80000000u;
 
-    // input rows are loaded kPF rows ahead of their use (a rolling queue)
-    constexpr int kPF = 12;
+    // input rows are loaded kPF rows ahead of their use (a rolling queue);
+    // border waves hold four byte loads per row, so they look fewer rows ahead
+    constexpr int kPF = BORDER ? 6 : 12;
     auto load_row = [&](int i) -> uint32_t {
         if (BORDER) {
             const int y = min(max(Y0 - 4 + i, 0), H - 1);
-            return load_px4(a.in + (int64_t)y * a.pitch, c0, W, fast);
+            return load_px4_clamped(a.in + (int64_t)y * a.pitch, c0, W);
         }
-        const uint8_t* rowp = uniform_ptr(a.in + (int64_t)(Y0 - 4 + i) * a.pitch);
-        return *reinterpret_cast<const uint32_t*>(rowp + (uint32_t)c0);
+        // buffer load: the row's base in scalar registers, the lane's offset
+        // in one vector register (c0 >= 0 for interior waves)
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<uint8_t*>(a.in + (int64_t)(Y0 - 4 + i) * a.pitch), (short)0, 0x7fffffff, 0x00020000);
+        return __builtin_amdgcn_raw_buffer_load_b32(rs, c0, 0, 0);
     };
     uint32_t q[kPF];
 #pragma unroll
@@ -233,11 +240,12 @@ __device__ __forceinline__ void walk(const U8FwdArgs& a, int X0, int Y0, int lan
         }
         if (i < 8) continue;
 
-        // ---- Step 3 + thresholds: row n = g - 1
+        // ---- Step 3 + thresholds: row n = g - 1 (rows past the image store nothing)
         const int n = g - 1;
-        if (BORDER && n >= H) continue;
         const uint32_t byte = classify4(mu, mc, md, dir_prev, low2, high2, vmask0, vmask1);
-        if (store_lane) uniform_ptr(a.cls + (int64_t)n * a.cpitch)[cls_off] = (uint8_t)byte;
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            a.cls + (int64_t)min(n, H - 1) * a.cpitch, (short)0, 0x7fffffff, 0x00020000);
+        __builtin_amdgcn_raw_buffer_store_b8((uint8_t)byte, rs, (int)(BORDER && n >= H ? 0x80000000u : soff), 0, 0);
     }
 }
 
@@ -255,8 +263,8 @@ k_u8_forward(U8FwdArgs a, int strips_x, int nwaves, int fast_ok) {
     const int Y0 = blk * R;
     const bool interior = fast_ok && X0 >= 4 && X0 + kU8StripCols + 4 <= a.W && Y0 >= 4 &&
                           Y0 + R + 4 <= a.H;
-    if (interior) walk<R, false>(a, X0, Y0, lane, true);
-    else walk<R, true>(a, X0, Y0, lane, fast_ok);
+    if (interior) walk<R, false>(a, X0, Y0, lane);
+    else walk<R, true>(a, X0, Y0, lane);
 }
 
 template <int RRI, int RRE>
@@ -290,9 +298,9 @@ k_u8_forward_bal(U8FwdArgs a, U8Plan p, int fast_ok) {
     if (interior) {
         if (!(fast_ok && X0 >= 4 && X0 + kU8StripCols + 4 <= a.W && Y0 >= 4 && Y0 + RRI + 4 <= a.H))
             return;  // unreachable for a plan from make_u8_plan
-        walk<RRI, false>(a, X0, Y0, lane, true);
+        walk<RRI, false>(a, X0, Y0, lane);
     } else {
-        walk<RRE, true>(a, X0, Y0, lane, fast_ok);
+        walk<RRE, true>(a, X0, Y0, lane);
     }
 }
 
@@ -331,8 +339,8 @@ k_u8_forward_batch(const BatchImage* imgs, const BatchDev* hdr) {
         const bool fast_ok = ((uintptr_t)a.in % 4 == 0) && (a.pitch % 4 == 0);
         const bool interior = fast_ok && X0 >= 4 && X0 + kU8StripCols + 4 <= a.W && Y0 >= 4 &&
                               Y0 + R + 4 <= a.H;
-        if (interior) walk<R, false>(a, X0, Y0, lane, true);
-        else walk<R, true>(a, X0, Y0, lane, fast_ok);
+        if (interior) walk<R, false>(a, X0, Y0, lane);
+        else walk<R, true>(a, X0, Y0, lane);
     }
 }
 
