@@ -9,6 +9,45 @@ namespace {
 
 struct F4 { float v[4]; };
 
+// The lane's 4 values of a row with its columns clamped into the image, as
+// four element loads through a buffer descriptor (row base in scalar
+// registers): the same instructions in every lane, so that the compiler
+// knows how many memory operations are outstanding and waits only for the
+// row it needs.  row must be wave-uniform.
+__device__ __forceinline__ F4 load_row_clamped(const float* row, int c0, int W) {
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(row), (short)0, 0x7fffffff, 0x00020000);
+    F4 r;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        r.v[k] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, min(max(c0 + k, 0), W - 1) * 4, 0, 0));
+    return r;
+}
+
+// The lane's 4 values of a (wave-uniform) row where ok[k] holds and 0
+// elsewhere: the others are loaded from an offset past the descriptor's range,
+// which reads as 0, so no select (and no wait) follows the loads.
+__device__ __forceinline__ F4 load_row_masked(const float* row, int c0, const bool* ok) {
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(row), (short)0, 0x7fffffff, 0x00020000);
+    F4 r;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        r.v[k] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, ok[k] ? (c0 + k) * 4 : (int)0x80000000, 0, 0));
+    return r;
+}
+
+// Stores x.v[k] at column c0 + k of a (wave-uniform) row where ok[k] holds;
+// the other elements get an offset past the descriptor's range and the
+// hardware drops them (no branch around the stores).
+__device__ __forceinline__ void store_row_masked(float* row, int c0, const F4& x, const bool* ok) {
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(row, (short)0, 0x7fffffff, 0x00020000);
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, x.v[k]), rs,
+                                              ok[k] ? (c0 + k) * 4 : (int)0x80000000, 0, 0);
+}
+
 __device__ __forceinline__ F4 load_row(const float* row, int c0, int W, bool fast) {
     F4 r;
     if (fast) {

@@ -186,7 +186,7 @@ __device__ __forceinline__ void push_terms(F4* dxw, F4* sxw, const F4& dx, const
 template <int R>
 __global__ void __launch_bounds__(kWGThreads)
 k_mag_fwd(const float* I, const float* sigma, int N, int H, int W, float* M, int strips_x,
-          int blocks_y, int fast_ok) {
+          int blocks_y) {
     constexpr int HL = (R + 1 + 3) / 4;
     constexpr int HR = R + 1;
     constexpr int NI = kMagRows + 2 * HR;
@@ -199,11 +199,10 @@ k_mag_fwd(const float* I, const float* sigma, int N, int H, int W, float* M, int
     const int c0 = wg.c0, X0 = wg.X0, Y0 = wg.Y0;
     const BorderF bd = make_border<HL>(X0, c0, W);
     const bool out_lane = wg.lane >= HL && wg.lane < kWave - HL;
-    const bool fast = fast_ok && c0 >= 0 && c0 + 4 <= W;
     const Taps<R> tp = make_taps<R>(sigma[wg.n]);
     auto fetch = [&](int i) -> F4 {
         const int y = min(max(Y0 - HR + i, 0), H - 1);
-        return load_row(img + (int64_t)y * W, c0, W, fast);
+        return load_row_clamped(img + (int64_t)y * W, c0, W);
     };
     F4 win[NW];
 #pragma unroll
@@ -232,15 +231,17 @@ k_mag_fwd(const float* I, const float* sigma, int N, int H, int W, float* M, int
         sobel_terms(B, dx, sx);
         push_terms(dxw, sxw, dx, sx, b, H);
         if (i < 2 * R + 2) continue;
-        const int gr = b - 1;
-        if (gr >= H || !out_lane) continue;
-        float* orow = out + (int64_t)gr * W;
+        const int gr = b - 1;  // >= Y0; rows past the image are dropped at the store
+        F4 m;
+        bool ok[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const float gx = fmaf(2.0f, dxw[1].v[k], dxw[0].v[k] + dxw[2].v[k]);
             const float gy = sxw[2].v[k] - sxw[0].v[k];
-            if (!bd.outR[k]) orow[c0 + k] = __builtin_amdgcn_sqrtf(fmaf(gx, gx, gy * gy));
+            m.v[k] = __builtin_amdgcn_sqrtf(fmaf(gx, gx, gy * gy));
+            ok[k] = gr < H && out_lane && !bd.outR[k];
         }
+        store_row_masked(out + (int64_t)min(gr, H - 1) * W, c0, m, ok);
     }
 }
 
@@ -248,7 +249,7 @@ k_mag_fwd(const float* I, const float* sigma, int N, int H, int W, float* M, int
 template <int R>
 __global__ void __launch_bounds__(kWGThreads)
 k_mag_bwd_a(const float* I, const float* sigma, const float* dM, int N, int H, int W, float* dB,
-            int strips_x, int blocks_y, int fast_ok) {
+            int strips_x, int blocks_y) {
     constexpr int HL = (R + 2 + 3) / 4;
     constexpr int HR = R + 2;
     constexpr int NI = kMagRows + 2 * HR;
@@ -263,11 +264,10 @@ k_mag_bwd_a(const float* I, const float* sigma, const float* dM, int N, int H, i
     const int c0 = wg.c0, X0 = wg.X0, Y0 = wg.Y0;
     const BorderF bd = make_border<HL>(X0, c0, W);
     const bool out_lane = wg.lane >= HL && wg.lane < kWave - HL;
-    const bool fast = fast_ok && c0 >= 0 && c0 + 4 <= W;
     const Taps<R> tp = make_taps<R>(sigma[wg.n]);
     auto fetch = [&](int i) -> F4 {
         const int y = min(max(Y0 - HR + i, 0), H - 1);
-        return load_row(img + (int64_t)y * W, c0, W, fast);
+        return load_row_clamped(img + (int64_t)y * W, c0, W);
     };
     F4 win[NW];
 #pragma unroll
@@ -280,10 +280,23 @@ k_mag_bwd_a(const float* I, const float* sigma, const float* dM, int N, int H, i
     bool inimg[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) inimg[k] = !bd.outL[k] && !bd.outR[k];
+    // dM row consumed at iteration i (i >= 2R + 2), loaded GD iterations
+    // earlier into a ring (compile-time slots in the unrolled loop)
+    constexpr int GD = 4;
+    auto gm_row = [&](int i) -> F4 {
+        const int gr = Y0 - HR + i - R - 1;
+        return load_row_clamped(gm + (int64_t)min(max(gr, 0), H - 1) * W, c0, W);
+    };
+    F4 gq[GD];
+#pragma unroll
+    for (int j = 2 * R + 2; j < GD && j < NI; ++j) gq[j % GD] = gm_row(j);  // due before iteration 0
     F4 dxw[3], sxw[3];
     F4 gxw[3], vw[3];  // rows gr-2 .. gr of dGx and of v = Sx^T dGy
 #pragma unroll
     for (int i = 0; i < NI; ++i) {
+        F4 gmv = {};
+        if (i >= 2 * R + 2) gmv = gq[i % GD];
+        if (i + GD >= 2 * R + 2 && i + GD < NI) gq[(i + GD) % GD] = gm_row(i + GD);  // i + GD >= GD
         if (i > 0) {
 #pragma unroll
             for (int k = 0; k < NW - 1; ++k) win[k] = win[k + 1];
@@ -304,8 +317,6 @@ k_mag_bwd_a(const float* I, const float* sigma, const float* dM, int N, int H, i
         // dG of row gr (zero outside the image: the adjoint reads it zero-extended)
         const int gr = b - 1;
         const bool row_in = gr >= 0 && gr < H;
-        F4 gmv = {};
-        if (row_in) gmv = load_row(gm + (int64_t)gr * W, c0, W, fast);
         F4 dgx, dgy;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -339,9 +350,9 @@ k_mag_bwd_a(const float* I, const float* sigma, const float* dM, int N, int H, i
         vw[0] = vw[1]; vw[1] = vw[2]; vw[2] = v;
         if (i < 2 * R + 4) continue;
 
-        // dB of row db = gr - 1 from dG rows db-1, db, db+1
+        // dB of row db = gr - 1 from dG rows db-1, db, db+1 (db >= Y0; rows
+        // past the image are dropped at the store)
         const int db = gr - 1;
-        if (db >= H) continue;
         F4 u, w;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -361,8 +372,8 @@ k_mag_bwd_a(const float* I, const float* sigma, const float* dM, int N, int H, i
             w.v[k] = ww;
         }
         const float ul = from_left_f(u.v[3]), ur = from_right_f(u.v[0]);
-        if (!out_lane) continue;
-        float* orow = out + (int64_t)db * W;
+        F4 res;
+        bool ok[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const float xm = k == 0 ? ul : u.v[k - 1];
@@ -374,8 +385,10 @@ k_mag_bwd_a(const float* I, const float* sigma, const float* dM, int N, int H, i
                 else if (x == 0) dxu = -u.v[k] - xp;
                 else if (x == W - 1) dxu = u.v[k] + xm;
             }
-            if (!bd.outR[k]) orow[x] = dxu + w.v[k];
+            res.v[k] = dxu + w.v[k];
+            ok[k] = db < H && out_lane && !bd.outR[k];
         }
+        store_row_masked(out + (int64_t)min(db, H - 1) * W, c0, res, ok);
     }
 }
 
@@ -383,7 +396,7 @@ k_mag_bwd_a(const float* I, const float* sigma, const float* dM, int N, int H, i
 template <int R>
 __global__ void __launch_bounds__(kWGThreads)
 k_mag_bwd_b(const float* I, const float* sigma, const float* dB, int N, int H, int W, float* dI,
-            float* partial, int strips_x, int blocks_y, int fast_ok) {
+            float* partial, int strips_x, int blocks_y) {
     constexpr int HL = (R + 3) / 4;
     constexpr int NI = kMagRows + 2 * R;
     constexpr int PF = 4;
@@ -397,36 +410,47 @@ k_mag_bwd_b(const float* I, const float* sigma, const float* dB, int N, int H, i
     const int c0 = wg.c0, X0 = wg.X0, Y0 = wg.Y0;
     const BorderF bd = make_border<HL>(X0, c0, W);
     const bool out_lane = wg.lane >= HL && wg.lane < kWave - HL;
-    const bool fast = fast_ok && c0 >= 0 && c0 + 4 <= W;
     const Taps<R> tp = make_taps<R>(sigma[wg.n]);
     bool inimg[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) inimg[k] = !bd.outL[k] && !bd.outR[k];
-    // dB rows Y0-R+i, zero outside the image
+    // dB rows Y0-R+i, zero outside the image (out-of-range loads read 0, so
+    // every row issues the same loads)
     auto fetch = [&](int i) -> F4 {
         const int y = Y0 - R + i;
-        F4 r = {};
-        if (y >= 0 && y < H) {
-            r = load_row(src + (int64_t)y * W, c0, W, fast);
+        const bool row_in = y >= 0 && y < H;
+        bool ok[4];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) r.v[k] = inimg[k] ? r.v[k] : 0.0f;
-        }
-        return r;
+        for (int k = 0; k < 4; ++k) ok[k] = row_in && inimg[k];
+        return load_row_masked(src + (int64_t)min(max(y, 0), H - 1) * W, c0, ok);
     };
+    // input row of output row y = Y0 - 2R + i, consumed at iteration i >= 2R,
+    // loaded GD iterations earlier into a ring
+    constexpr int GD = 4;
+    auto in_row = [&](int i) -> F4 {
+        const int y = Y0 - 2 * R + i;
+        return load_row_clamped(img + (int64_t)min(y, H - 1) * W, c0, W);
+    };
+    F4 iq[GD];
+#pragma unroll
+    for (int j = 2 * R; j < GD && j < NI; ++j) iq[j % GD] = in_row(j);  // due before iteration 0
     F4 win[NW];
 #pragma unroll
     for (int k = 0; k < NW; ++k) win[k] = (k >= 2 * R && k - 2 * R < NI) ? fetch(k - 2 * R) : F4{};
     float acc = 0.0f;
 #pragma unroll
     for (int i = 0; i < NI; ++i) {
+        F4 Ir = {};
+        if (i >= 2 * R) Ir = iq[i % GD];
+        if (i + GD >= 2 * R && i + GD < NI) iq[(i + GD) % GD] = in_row(i + GD);  // i + GD >= GD
         if (i > 0) {
 #pragma unroll
             for (int k = 0; k < NW - 1; ++k) win[k] = win[k + 1];
             if (i + PF < NI) win[NW - 1] = fetch(i + PF);
         }
         if (i < 2 * R) continue;
-        const int y = Y0 - R + i - R;  // output row
-        if (y >= H) continue;
+        const int y = Y0 - R + i - R;  // output row (>= Y0); rows past the image are dropped
+        const bool row_ok = y < H;
         // dT = Gv^T dB and dT' = Gv'^T dB at row y
         F4 dT, dTp;
         const bool edge_row = y == 0 || y == H - 1;
@@ -454,8 +478,7 @@ k_mag_bwd_b(const float* I, const float* sigma, const float* dB, int N, int H, i
             dT.v[k] = a0;
             dTp.v[k] = a1;
         }
-        // T = Gh I and T' = Gh' I of the input row y (clamped reads)
-        const F4 Ir = load_row(img + (int64_t)y * W, c0, W, fast);
+        // T = Gh I and T' = Gh' I of the input row y (clamped reads, Ir above)
         float ext[4 + 2 * R];
 #pragma unroll
         for (int e = -R; e < 4 + R; ++e) ext[e + R] = lane_ext(Ir, e);
@@ -463,8 +486,8 @@ k_mag_bwd_b(const float* I, const float* sigma, const float* dB, int N, int H, i
         float dext[4 + 2 * R];
 #pragma unroll
         for (int e = -R; e < 4 + R; ++e) dext[e + R] = lane_ext(dT, e);
-        if (!out_lane) continue;
-        float* orow = out + (int64_t)y * W;
+        F4 res;
+        bool ok[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             float t0 = tp.g[0] * ext[k + R], t1 = tp.dg[0] * ext[k + R];
@@ -485,11 +508,11 @@ k_mag_bwd_b(const float* I, const float* sigma, const float* dB, int N, int H, i
 #pragma unroll
                 for (int j = 1; j <= R; ++j) di = fmaf(tp.g[j], dext[k + R - j] + dext[k + R + j], di);
             }
-            if (inimg[k]) {
-                orow[x] = di;
-                acc = fmaf(dT.v[k], t1, fmaf(dTp.v[k], t0, acc));
-            }
+            res.v[k] = di;
+            ok[k] = row_ok && out_lane && inimg[k];
+            acc = ok[k] ? fmaf(dT.v[k], t1, fmaf(dTp.v[k], t0, acc)) : acc;
         }
+        store_row_masked(out + (int64_t)min(y, H - 1) * W, c0, res, ok);
     }
     // fixed-order wave reduction of the dsigma partial
 #pragma unroll
@@ -536,9 +559,8 @@ template <int R>
 hipError_t fwd_r(const float* I, const float* sigma, int N, int H, int W, float* M, hipStream_t s) {
     constexpr int HL = (R + 1 + 3) / 4;
     const Grid g = grid_for<HL>(N, H, W);
-    const int fast_ok = ((uintptr_t)I % 16 == 0) && (W % 4 == 0);
     hipLaunchKernelGGL(k_mag_fwd<R>, dim3(g.nwg), dim3(kWGThreads), 0, s, I, sigma, N, H, W, M,
-                       g.strips_x, g.blocks_y, fast_ok);
+                       g.strips_x, g.blocks_y);
     return hipGetLastError();
 }
 
@@ -547,11 +569,10 @@ hipError_t bwd_r(const float* I, const float* sigma, const float* dM, int N, int
                  float* dsigma, float* dB, float* partial, hipStream_t s) {
     constexpr int HLA = (R + 2 + 3) / 4, HLB = (R + 3) / 4;
     const Grid ga = grid_for<HLA>(N, H, W), gb = grid_for<HLB>(N, H, W);
-    const int fast_ok = ((uintptr_t)I % 16 == 0) && ((uintptr_t)dM % 16 == 0) && (W % 4 == 0);
     hipLaunchKernelGGL(k_mag_bwd_a<R>, dim3(ga.nwg), dim3(kWGThreads), 0, s, I, sigma, dM, N, H, W, dB,
-                       ga.strips_x, ga.blocks_y, fast_ok);
+                       ga.strips_x, ga.blocks_y);
     hipLaunchKernelGGL(k_mag_bwd_b<R>, dim3(gb.nwg), dim3(kWGThreads), 0, s, I, sigma, dB, N, H, W, dI,
-                       partial, gb.strips_x, gb.blocks_y, fast_ok);
+                       partial, gb.strips_x, gb.blocks_y);
     hipLaunchKernelGGL(k_mag_reduce, dim3(N), dim3(kWGThreads), 0, s, partial, gb.per_img, dsigma);
     return hipGetLastError();
 }
