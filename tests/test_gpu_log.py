@@ -58,6 +58,22 @@ def test_log_7680x4320_and_odd(canny):
     check(canny, workloads.natural_u8(1001, 2049, seed=3), 6, "odd")
 
 
+@pytest.mark.parametrize("H,W", [(7, 9), (129, 1000), (512, 512), (1001, 2049), (4096, 4096)])
+def test_log_edges_only(canny, H, W):
+    """Edges without the Laplacian output (the launch variant the benchmark
+    runs: 4-byte stores into an aligned edge buffer, no Laplacian stores):
+    equal to the oracle and to the run that also writes the Laplacian."""
+    img = workloads.natural_u8(H, W, seed=H + 7 * W)
+    print(f"[log] edges only {H}x{W}", flush=True)
+    dev = torch.from_numpy(img).cuda()
+    e = canny.canny_log_u8(dev, 10)
+    e2, _ = canny.canny_log_u8(dev, 10, return_laplacian=True)
+    torch.cuda.synchronize()
+    oe, _ = oracle.log_u8(img, 10)
+    assert np.array_equal(e.cpu().numpy(), oe)
+    assert torch.equal(e, e2)
+
+
 def test_log_unaligned(canny):
     """Rows whose start is not 4-byte aligned and odd pitches for the input,
     an odd-pitch edge buffer (byte stores)."""
