@@ -48,18 +48,6 @@ __device__ __forceinline__ void store_row_masked(float* row, int c0, const F4& x
                                               ok[k] ? (c0 + k) * 4 : (int)0x80000000, 0, 0);
 }
 
-__device__ __forceinline__ F4 load_row(const float* row, int c0, int W, bool fast) {
-    F4 r;
-    if (fast) {
-        const float4 q = *reinterpret_cast<const float4*>(row + c0);
-        r.v[0] = q.x; r.v[1] = q.y; r.v[2] = q.z; r.v[3] = q.w;
-    } else {
-#pragma unroll
-        for (int k = 0; k < 4; ++k) r.v[k] = row[min(max(c0 + k, 0), W - 1)];
-    }
-    return r;
-}
-
 // value of a strip row at column offset e (relative to the lane's c0), for
 // e in [-16, 19]: own 4 values, up to 4 lanes to the left or right
 __device__ __forceinline__ float lane_ext(const F4& x, int e) {

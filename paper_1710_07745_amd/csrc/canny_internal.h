@@ -42,16 +42,6 @@ __device__ __forceinline__ uint32_t from_right(uint32_t v) {
 __device__ __forceinline__ float from_left_f(float v) { return bc<float>(from_left(bc<uint32_t>(v))); }
 __device__ __forceinline__ float from_right_f(float v) { return bc<float>(from_right(bc<uint32_t>(v))); }
 
-// A pointer the caller knows to be wave-uniform, moved to scalar registers so
-// that per-lane accesses use the scalar-base + 32-bit-offset address form.
-template <typename T>
-__device__ __forceinline__ T* uniform_ptr(T* p) {
-    const uint64_t v = reinterpret_cast<uint64_t>(p);
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-    return reinterpret_cast<T*>(((uint64_t)hi << 32) | lo);
-}
-
 // Workgroup index remapped so that each XCD (8 per chip, fed round-robin)
 // walks a contiguous range of logical workgroups.
 __device__ __forceinline__ int xcd_remap(int wg, int nwg) {

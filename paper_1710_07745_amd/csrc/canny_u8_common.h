@@ -65,17 +65,6 @@ __device__ __forceinline__ uint32_t load_px4_clamped(const uint8_t* row, int c0,
     return v;
 }
 
-__device__ __forceinline__ uint32_t load_px4(const uint8_t* row, int c0, int W, bool fast) {
-    if (fast) return *reinterpret_cast<const uint32_t*>(row + c0);
-    uint32_t v = 0;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        int c = min(max(c0 + k, 0), W - 1);
-        v |= (uint32_t)row[c] << (8 * k);
-    }
-    return v;
-}
-
 // Horizontal 5-tap binomial of the lane's 4 pixels (needs 2 from each side).
 __device__ __forceinline__ void hblur(uint32_t d, uint32_t& h0, uint32_t& h1) {
     const uint32_t dl = from_left(d), dr = from_right(d);
