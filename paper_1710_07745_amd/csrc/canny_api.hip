@@ -33,8 +33,9 @@ bool device_ok() {
     return cached[dev] == 1;
 }
 
-// Sizes whose tile-rounded pixel count fits the 31-bit component names of
-// the hysteresis pass (e.g. 46000 x 46000).
+// Sizes whose tile-rounded pixel count fits 31 bits (e.g. 46000 x 46000):
+// pixel offsets of the tiles, and the hysteresis pass's component names
+// (below 2^27) with their weak bit, stay within int32.
 bool size_ok(int H, int W) {
     return H >= 1 && W >= 1 && H <= (1 << 20) && W <= (1 << 20) &&
            (int64_t)ceil_div(H, 64) * ceil_div(W, 64) * 4096 < ((int64_t)1 << 31);

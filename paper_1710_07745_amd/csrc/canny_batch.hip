@@ -5,11 +5,11 @@
 // image (class map + hysteresis state).  Every phase of the detector runs as
 // ONE flat launch over all images: one wave per forward task (a strip and row
 // block of one image), one workgroup per hysteresis tile for the local and
-// resolve passes, one thread per border pixel or slot for merge and flags.
+// resolve passes, one thread per right or bottom border pixel for merge.
 // Work items are uniform, so large and small images interleave freely and no
 // shared counter is touched; a tile's image comes from a per-plan
 // tile -> image table.  The launches are recorded once into a HIP graph
-//     forward -> local -> merge -> flags -> resolve
+//     forward -> local -> merge -> resolve
 // whose kernels read a device descriptor table; a call uploads the table
 // (the caller's image pointers and workspace) and replays the graph, so new
 // buffers never need a new recording.
@@ -89,7 +89,7 @@ __global__ void k_fill_texture(uint8_t* p, int64_t n, uint32_t seed) {
 
 void layout(canny_batch_plan& p, const int32_t* H, const int32_t* W) {
     size_t off = 0;
-    int tile_base = 0, merge_base = 0, slot_base = 0;
+    int tile_base = 0, merge_base = 0;
     p.imgs.resize(p.n);
     for (int i = 0; i < p.n; ++i) {
         BatchImage& m = p.imgs[i];
@@ -104,7 +104,6 @@ void layout(canny_batch_plan& p, const int32_t* H, const int32_t* W) {
         hyst_carve(base, m.H, m.W, kT, h);
         m.blab_off = (int64_t)off + (reinterpret_cast<char*>(h.blab) - base);
         m.parent_off = (int64_t)off + (reinterpret_cast<char*>(h.parent) - base);
-        m.flag_off = (int64_t)off + (reinterpret_cast<char*>(h.flag) - base);
         m.pmask_off = (int64_t)off + (reinterpret_cast<char*>(h.pmask) - base);
         off += al256(hyst_workspace_bytes(m.H, m.W, kT));
         m.tiles_x = ceil_div(m.W, kHystCols);
@@ -112,10 +111,8 @@ void layout(canny_batch_plan& p, const int32_t* H, const int32_t* W) {
         const int ntiles = m.tiles_x * m.tiles_y;
         m.tile_base = tile_base;
         m.merge_base = merge_base;
-        m.slot_base = slot_base;
         tile_base += ntiles;
         merge_base += ntiles * (kT + kHystCols);
-        slot_base += ntiles * kPerimT;
     }
     p.ws_bytes = off;
     p.hdr.n = p.n;
@@ -123,7 +120,6 @@ void layout(canny_batch_plan& p, const int32_t* H, const int32_t* W) {
     p.hdr.high = p.high;
     p.hdr.total_tiles = tile_base;
     p.hdr.total_merge = merge_base;
-    p.hdr.total_slots = slot_base;
 }
 
 void set_fwd_rows(canny_batch_plan& p, int rows) {
@@ -140,8 +136,7 @@ void set_fwd_rows(canny_batch_plan& p, int rows) {
 hipError_t enqueue(const canny_batch_plan& p, hipStream_t s) {
     hipError_t e = launch_u8_forward_batch(p.d_imgs, p.d_hdr, p.fwd_rows, p.hdr.total_fwd, s);
     if (e != hipSuccess) return e;
-    return launch_hyst_batch(p.d_imgs, p.d_hdr, p.hdr.total_tiles, p.hdr.total_merge,
-                             p.hdr.total_slots, s);
+    return launch_hyst_batch(p.d_imgs, p.d_hdr, p.hdr.total_tiles, p.hdr.total_merge, s);
 }
 
 // synchronous upload of the table (plan creation and tuning only)
@@ -312,7 +307,7 @@ int canny_batch_plan_create(int n, const int32_t* H, const int32_t* W, int32_t l
         tiles += (int64_t)ceil_div(H[i], kT) * ceil_div(W[i], kHystCols);
         px += (int64_t)H[i] * W[i];
     }
-    // flat per-pixel / per-slot grids of the batch use 31-bit indices
+    // flat per-pixel / per-merge-item grids of the batch use 31-bit indices
     if (tiles * (kT + kHystCols) >= ((int64_t)1 << 31) || tiles * kPerimT >= ((int64_t)1 << 31) ||
         px / 16 >= ((int64_t)1 << 31))
         return CANNY_ERR_INVALID;

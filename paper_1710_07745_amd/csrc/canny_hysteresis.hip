@@ -5,7 +5,7 @@
 // paper keeps this step serial; here it is union-find, whose cost does not
 // grow with the length of a propagation chain.
 //
-// The image is cut into 64-column x T-row tiles.  Four launches:
+// The image is cut into 64-column x T-row tiles.  Three launches:
 //   1. local:  each workgroup labels its tile in LDS.  Candidates in a row
 //              form runs; a run is 8-connected to the runs of the row above
 //              that meet columns c0 - 1 .. c1 + 1.  Each run start first
@@ -13,24 +13,29 @@
 //              flattens the resulting trees, and union-find (atomicMin, roots
 //              = smallest pixel index) joins the remaining pairs, which only
 //              occur where two branches meet; every run start then finds its
-//              root.  A component that does not touch the tile border is
-//              decided here: its pixels get 255 if it holds a
-//              strong pixel, else 0.  A component that touches the border is
-//              named globally by tile * 256 + b, b (0..251) the largest index
-//              of its border pixels; the pass writes, per tile-border pixel,
-//              that name (or -1), initialises parent/flag for it (dense arrays
-//              of 256 entries per tile, indexed by name), and gives its pixels
-//              the pending code 1 + b.  Non-candidates get 0.
+//              root.  A component that is decided here -- it holds a
+//              strong pixel, or it does not touch the tile border -- gets 255
+//              or 0.  A component that touches the border is named globally
+//              by tile * 256 + b, b (0..251) the largest index of its border
+//              pixels.  Its union-find key is that name, plus 2^30 if the
+//              component holds no strong pixel in the tile.  The pass
+//              writes, per tile-border pixel, that key (or -1), initialises
+//              the name's parent entry (a dense array of 256 entries per
+//              tile, indexed by name) with it, and gives the pixels of a weak
+//              border component the pending code 1 + b.  Non-candidates
+//              get 0.
 //   2. merge:  one thread per tile-border pixel on the right and bottom tile
 //              edges unions its component with the 8-connected candidates
-//              across the edge (global union-find, atomicMin linking).
-//   3. flags:  one thread per border slot finds its component's root
-//              (read-only walk), stores it in the name's entry (flattening
-//              the forest) and in the slot, and ORs the component's strong
-//              flag into the root's.
-//   4. resolve: each workgroup rewrites the pending pixels of its tile to
-//              255 / 0 from the flag of the root named by the border pixel
-//              the code points at.
+//              across the edge (global union-find over keys, atomicMin
+//              linking: a root always links under a smaller key).  A set's
+//              root therefore holds its smallest key, which is below 2^30
+//              exactly when some component of the set holds a strong pixel:
+//              the roots carry the global strong flags without a pass of
+//              their own.
+//   3. resolve: each workgroup with pending pixels walks the keys of its
+//              weak border components towards their roots, stopping at the
+//              first strong key (keys fall along a path, so the root is then
+//              strong as well), and rewrites the pending pixels to 255 / 0.
 // Border slots of a tile (clipped to the image): top row x -> x, bottom row
 // x -> 64 + x, left column y -> 128 + y, right column y -> 128 + T + y.
 // Border pixel index b (each border pixel once, for the pending code): top
@@ -85,19 +90,26 @@ __device__ __forceinline__ void lds_union(int* L, int a, int b) {
     }
 }
 
+// Union-find keys of border components: the global name, plus kWeakKey for a
+// component without a strong pixel.  Names stay below 2^27 (at most 2^19
+// tiles of 256 names), so a key fits 31 bits and -1 stays free for "none".
+constexpr int kWeakKey = 1 << 30;
+constexpr int kNameMask = kWeakKey - 1;
+
 __device__ __forceinline__ int g_load(const int* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Parent pointers only ever point to smaller names, so a walk from x ends
-// within x + 1 steps; the bound makes that explicit.
-__device__ __forceinline__ int g_find(int* parent, int x) {
-    int p = g_load(parent + x);
-    for (int steps = x; p != x && steps >= 0; --steps) {
-        x = p;
-        p = g_load(parent + x);
+// parent[name] holds a key: the entry's own key at a root, else a smaller
+// one.  Keys strictly fall along a walk, so a walk from key k ends within
+// k + 1 steps; the bound makes that explicit.
+__device__ __forceinline__ int g_find(int* parent, int k) {
+    int p = g_load(parent + (k & kNameMask));
+    for (int steps = k; p != k && steps >= 0; --steps) {
+        k = p;
+        p = g_load(parent + (k & kNameMask));
     }
-    return x;
+    return k;
 }
 
 __device__ __forceinline__ void g_union(int* parent, int a, int b) {
@@ -106,7 +118,7 @@ __device__ __forceinline__ void g_union(int* parent, int a, int b) {
         b = g_find(parent, b);
         if (a == b) return;
         if (a < b) { const int t = a; a = b; b = t; }
-        const int old = atomicMin(parent + a, b);
+        const int old = atomicMin(parent + (a & kNameMask), b);
         if (old == a) return;
         a = old;
     }
@@ -585,10 +597,11 @@ __device__ __forceinline__ void local_tile(const HystArgs& a, const TileGeom& g,
     const int r = t / TL::kTPR;
     const int cb = (t % TL::kTPR) * TL::kPPT;
     const int me = r * kHystCols;
-    // every candidate: 255 / 0 for a component inside the tile (by its strong
-    // bit), the pending code 1 + b for one that touches the border (b its
-    // largest border index); one lookup per run that covers pixels of the
-    // segment (the first may start in an earlier segment)
+    // every candidate: 255 for a component with a strong pixel, 0 for one
+    // without that stays inside the tile, the pending code 1 + b for one
+    // without that touches the border (b its largest border index); one
+    // lookup per run that covers pixels of the segment (the first may start
+    // in an earlier segment)
     bool pending = false;
     if (r < g.th) {
         uint32_t w[4] = {0u, 0u, 0u, 0u};
@@ -600,8 +613,9 @@ __device__ __forceinline__ void local_tile(const HystArgs& a, const TileGeom& g,
             const int root = L[me + s0] & kRootMask;
             const uint32_t br = (uint32_t)L[root] >> kBrepShift;
             const bool strong = (sm.strong[root >> 5] >> (root & 31)) & 1u;
-            pending |= br != 0;
-            const uint32_t v = (br ? br : (strong ? 255u : 0u)) * 0x01010101u;
+            const bool pend = br != 0 && !strong;
+            pending |= pend;
+            const uint32_t v = (pend ? br : (strong ? 255u : 0u)) * 0x01010101u;
             const uint32_t span = ((2u << k1) - 1u) & ~((1u << k0) - 1u);
 #pragma unroll
             for (int q = 0; q < 4; ++q)  // bit j of a nibble -> byte j (0x00 / 0xFF)
@@ -616,9 +630,9 @@ __device__ __forceinline__ void local_tile(const HystArgs& a, const TileGeom& g,
     // one bit per thread segment with pending codes, one word per wave
     const uint64_t pm = __ballot(pending);
     if ((t & (kWave - 1)) == 0) a.pmask[(int64_t)g.tile * (kWGThreads / kWave) + t / kWave] = pm;
-    // the global name of every border slot's component (-1: no candidate);
-    // the slot of the pixel whose border index names the component starts its
-    // union-find entry
+    // the union-find key of every border slot's component (-1: no
+    // candidate); the slot of the pixel whose border index names the
+    // component starts its union-find entry
     const int base = g.tile * TL::kPerim;
     for (int s = t; s < TL::kPerim; s += kWGThreads) {
         int pr, pc;
@@ -627,19 +641,17 @@ __device__ __forceinline__ void local_tile(const HystArgs& a, const TileGeom& g,
         else if (s < 2 * kHystCols) { pr = g.th - 1; pc = s - kHystCols; in = pc < g.tw; }
         else if (s < 2 * kHystCols + T) { pr = s - 2 * kHystCols; pc = 0; in = pr < g.th; }
         else { pr = s - 2 * kHystCols - T; pc = g.tw - 1; in = pr < g.th; }
-        int name = -1;
+        int key = -1;
         const uint64_t mr = in ? sm.cm[pr] : 0ull;
         if ((mr >> pc) & 1ull) {
             const int root = L[pr * kHystCols + run_start(mr & ~(mr << 1), pc)] & kRootMask;
             const int br = (int)((uint32_t)L[root] >> kBrepShift);  // >= 1 on the border
-            name = g.tile * kNamesPerTile + br - 1;
+            const int name = g.tile * kNamesPerTile + br - 1;
+            key = (sm.strong[root >> 5] >> (root & 31)) & 1u ? name : name | kWeakKey;
             const int bi = border_index(pr, pc, g.th, g.tw);
-            if (bi == br - 1 && border_slot<T>(bi) == s) {
-                a.parent[name] = name;
-                a.flag[name] = (sm.strong[root >> 5] >> (root & 31)) & 1u;
-            }
+            if (bi == br - 1 && border_slot<T>(bi) == s) a.parent[name] = key;
         }
-        a.blab[base + s] = name;
+        a.blab[base + s] = key;
     }
 }
 
@@ -658,7 +670,8 @@ __global__ void __launch_bounds__(kWGThreads) k_hyst_local(HystArgs a, int tiles
 }
 
 // Pass 2 for border pixel k of a tile (k < T: right edge row k; else bottom
-// edge column k - T).
+// edge column k - T).  Two components that are both strong need no union:
+// every set that either one joins is strong anyway.
 template <int T>
 __device__ __forceinline__ void merge_one(const HystArgs& a, int tile, int k, int tiles_x, int tiles_y) {
     using TL = Tile<T>;
@@ -674,7 +687,7 @@ __device__ __forceinline__ void merge_one(const HystArgs& a, int tile, int k, in
             if (qy < 0 || qy >= a.H) continue;
             const int qty = qy / T, qr = qy - qty * T;
             const int gq = a.blab[(qty * tiles_x + qx_tile) * TL::kPerim + 2 * kHystCols + qr];
-            if (gq >= 0) g_union(a.parent, gp, gq);
+            if (gq >= 0 && (gp | gq) >= kWeakKey) g_union(a.parent, gp, gq);
         }
     } else {  // bottom tile edge: pixel (th-1, c) against row Y0+T
         const int c = k - T;
@@ -686,7 +699,7 @@ __device__ __forceinline__ void merge_one(const HystArgs& a, int tile, int k, in
             if (qx < 0 || qx >= a.W) continue;
             const int qtx = qx / kHystCols, qc = qx - qtx * kHystCols;
             const int gq = a.blab[((g.ty + 1) * tiles_x + qtx) * TL::kPerim + qc];
-            if (gq >= 0) g_union(a.parent, gp, gq);
+            if (gq >= 0 && (gp | gq) >= kWeakKey) g_union(a.parent, gp, gq);
         }
     }
 }
@@ -701,56 +714,44 @@ k_hyst_merge(HystArgs a, int tiles_x, int tiles_y, int ntiles) {
     merge_one<T>(a, tile, (int)(gid - (int64_t)tile * per_tile), tiles_x, tiles_y);
 }
 
-// Pass 3 for border slot s.
-__device__ __forceinline__ void flags_one(const HystArgs& a, int s) {
-    const int gid = a.blab[s];
-    if (gid < 0) return;
-    // Find with path halving: every visited entry is replaced by its
-    // grandparent, so a pointer only ever moves to an ancestor and the long
-    // chains that simultaneous unions leave along an edge crossing many tiles
-    // shrink for the other slots walking them (a 4096^2 spiral: this pass
-    // 15.8 -> 10.5 us against a read-only walk; the same halving in the merge
-    // pass's finds made that pass slower).  Pointers decrease, so a walk ends
-    // within gid + 1 steps.
-    int x = gid;
-    for (int steps = gid; steps >= 0; --steps) {
-        const int p = a.parent[x];
-        if (p == x) break;
-        const int gp = a.parent[p];
-        if (gp == p) {
-            x = p;
-            break;
-        }
-        a.parent[x] = gp;
-        x = gp;
+// Whether the set of key k holds a strong pixel: walk towards the root until
+// a strong key (then the root's, smaller still, is strong too) or a weak root.
+// Path halving: each visited entry gets its grandparent, an ancestor, so the
+// long chains that simultaneous unions leave along an edge crossing many
+// tiles shrink for the other threads walking them.  No union runs during
+// this pass, so a halving store never overwrites a root.
+__device__ __forceinline__ bool key_strong(int* parent, int k) {
+    for (int steps = k; steps >= 0; --steps) {
+        if (k < kWeakKey) return true;
+        const int p = parent[k & kNameMask];
+        if (p == k) return false;
+        if (p < kWeakKey) return true;
+        const int gp = parent[p & kNameMask];
+        if (gp == p) return false;
+        parent[k & kNameMask] = gp;
+        k = gp;
     }
-    a.parent[gid] = x;
-    a.blab[s] = x;  // the slot now names the root: one load less in the resolve pass
-    if (a.flag[gid]) a.flag[x] = 1;
+    return false;  // not reached: keys fall along a walk
 }
 
-__global__ void __launch_bounds__(kWGThreads) k_hyst_flags(HystArgs a, int nslots) {
-    const int s = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (s < nslots) flags_one(a, s);
-}
-
-// Pass 4 on one tile: pending codes 1..252 become 255 / 0 by the global flag
-// of their component; everything else is already final.  Only the thread
-// segments the local pass marked in pmask are read and rewritten (a tile
-// without any is skipped); the workgroup resolves every border pixel index
-// once (res: LDS, 252 entries), so each pending pixel costs one LDS read.
+// Pass 3 on one tile: pending codes 1..252 become 255 / 0 by whether the set
+// of that border component holds a strong pixel; everything else is already
+// final.  Only the thread segments the local pass marked in pmask are read
+// and rewritten (a tile without any is skipped); the workgroup resolves every
+// border pixel index once (res: LDS, 252 entries), so each pending pixel
+// costs one LDS read.
 template <int T>
 __device__ __forceinline__ void resolve_tile(const HystArgs& a, int tile, int tiles_x, int vec16,
                                              uint8_t* res) {
     using TL = Tile<T>;
     static_assert(kWGThreads >= 3 * kHystCols + T - 4, "one thread per border pixel index");
     const int t = threadIdx.x;
-    // the border names (roots since the flags pass) are loaded together with
-    // the pending masks, so a tile with pending segments waits for two
-    // dependent loads (masks and names, then segments and root flags), not three
+    // the border keys are loaded together with the pending masks, so a tile
+    // with pending segments waits for two dependent loads (masks and keys,
+    // then segments and the keys' parents) where a walk stops at once
     const bool bthr = t < 2 * kHystCols + 2 * (T - 2);
-    int root = -1;
-    if (bthr) root = a.blab[(int64_t)tile * TL::kPerim + border_slot<T>(t)];
+    int key = -1;
+    if (bthr) key = a.blab[(int64_t)tile * TL::kPerim + border_slot<T>(t)];
     // segments with pending codes (the local pass's masks; identical reads in
     // every thread, so the early exit below is uniform)
     const uint64_t* pmt = a.pmask + (int64_t)tile * (kWGThreads / kWave);
@@ -769,7 +770,7 @@ __device__ __forceinline__ void resolve_tile(const HystArgs& a, int tile, int ti
         const int col0 = g.X0 + cb;
         out = load_seg(dst, valid, vec16, col0 >= 4 && col0 + TL::kPPT + 4 <= a.W);
     }
-    if (bthr) res[t] = root >= 0 && a.flag[root] ? 255 : 0;
+    if (bthr) res[t] = key >= 0 && key_strong(a.parent, key) ? 255 : 0;
     __syncthreads();
     if (!mine) return;
 #pragma unroll
@@ -793,14 +794,11 @@ hipError_t launch_t(const HystArgs& a, hipStream_t s) {
     const int tiles_x = ceil_div(a.W, kHystCols);
     const int tiles_y = ceil_div(a.H, T);
     const int ntiles = tiles_x * tiles_y;
-    const int nslots = ntiles * TL::kPerim;
     const int vec16 = ((uintptr_t)a.edges % 16 == 0) && (a.epitch % 16 == 0);
     hipLaunchKernelGGL(k_hyst_local<T>, dim3(ntiles), dim3(kWGThreads), 0, s, a, tiles_x, vec16);
     const int64_t nmerge = (int64_t)ntiles * (T + kHystCols);
     hipLaunchKernelGGL(k_hyst_merge<T>, dim3((unsigned)ceil_div64(nmerge, kWGThreads)),
                        dim3(kWGThreads), 0, s, a, tiles_x, tiles_y, ntiles);
-    hipLaunchKernelGGL(k_hyst_flags, dim3(ceil_div(nslots, kWGThreads)), dim3(kWGThreads), 0, s,
-                       a, nslots);
     hipLaunchKernelGGL(k_hyst_resolve<T>, dim3(ntiles), dim3(kWGThreads), 0, s, a, tiles_x, vec16);
     return hipGetLastError();
 }
@@ -816,14 +814,13 @@ __device__ __forceinline__ HystArgs batch_args(const BatchImage& im, char* ws) {
     a.epitch = im.epitch;
     a.blab = reinterpret_cast<int32_t*>(ws + im.blab_off);
     a.parent = reinterpret_cast<int32_t*>(ws + im.parent_off);
-    a.flag = reinterpret_cast<uint8_t*>(ws + im.flag_off);
     a.pmask = reinterpret_cast<uint64_t*>(ws + im.pmask_off);
     return a;
 }
 
 // Batch passes: flat grids over all images; a tile's image comes from the
-// plan's tile -> image table (merge items and border slots are 128 and 256
-// per tile, in tile order, so they index the same table).
+// plan's tile -> image table (merge items are 128 per tile, in tile order,
+// so they index the same table).
 template <int T>
 __global__ void __launch_bounds__(kWGThreads)
 k_hyst_local_batch(const BatchImage* imgs, const BatchDev* hdr) {
@@ -847,13 +844,6 @@ __global__ void __launch_bounds__(kWGThreads) k_hyst_merge_batch(const BatchImag
     merge_one<T>(batch_args(im, hdr->ws), tile, local - tile * (T + kHystCols), im.tiles_x, im.tiles_y);
 }
 
-__global__ void __launch_bounds__(kWGThreads) k_hyst_flags_batch(const BatchImage* imgs, const BatchDev* hdr) {
-    const int g = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (g >= hdr->total_slots) return;
-    const BatchImage& im = imgs[hdr->tile_img[g / Tile<64>::kPerim]];
-    flags_one(batch_args(im, hdr->ws), g - im.slot_base);
-}
-
 template <int T>
 __global__ void __launch_bounds__(kWGThreads)
 k_hyst_resolve_batch(const BatchImage* imgs, const BatchDev* hdr) {
@@ -870,13 +860,11 @@ k_hyst_resolve_batch(const BatchImage* imgs, const BatchDev* hdr) {
 }  // namespace
 
 hipError_t launch_hyst_batch(const BatchImage* imgs, const BatchDev* hdr, int total_tiles,
-                             int total_merge, int total_slots, hipStream_t s) {
+                             int total_merge, hipStream_t s) {
     constexpr int T = 64;
     hipLaunchKernelGGL(k_hyst_local_batch<T>, dim3(max(total_tiles, 1)), dim3(kWGThreads), 0, s,
                        imgs, hdr);
     hipLaunchKernelGGL(k_hyst_merge_batch<T>, dim3(ceil_div(max(total_merge, 1), kWGThreads)),
-                       dim3(kWGThreads), 0, s, imgs, hdr);
-    hipLaunchKernelGGL(k_hyst_flags_batch, dim3(ceil_div(max(total_slots, 1), kWGThreads)),
                        dim3(kWGThreads), 0, s, imgs, hdr);
     hipLaunchKernelGGL(k_hyst_resolve_batch<T>, dim3(max(total_tiles, 1)), dim3(kWGThreads), 0, s,
                        imgs, hdr);
@@ -889,14 +877,13 @@ static int perim(int tile_rows) { return 2 * kHystCols + 2 * tile_rows; }
 
 static size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-// blab: int32 per border slot; parent: int32 and flag: one byte per
-// component name (256 per tile; only the names of this call's border
-// components are written and read); pmask: one 64-bit word per wave of a
-// tile.  About 0.57 B per pixel.
+// blab: int32 per border slot; parent: int32 per component name (256 per
+// tile; only the names of this call's border components are written and
+// read); pmask: one 64-bit word per wave of a tile.  About 0.55 B per pixel.
 size_t hyst_workspace_bytes(int H, int W, int tile_rows) {
     const size_t ntiles = (size_t)ceil_div(W, kHystCols) * ceil_div(H, tile_rows);
     const size_t nnames = ntiles * (size_t)kNamesPerTile;
-    return al256(ntiles * perim(tile_rows) * 4) + al256(nnames * 4) + al256(nnames) +
+    return al256(ntiles * perim(tile_rows) * 4) + al256(nnames * 4) +
            al256(ntiles * (kWGThreads / kWave) * 8);
 }
 
@@ -908,8 +895,6 @@ void hyst_carve(void* ws, int H, int W, int tile_rows, HystArgs& a) {
     p += al256(ntiles * perim(tile_rows) * 4);
     a.parent = reinterpret_cast<int32_t*>(p);
     p += al256(nnames * 4);
-    a.flag = reinterpret_cast<uint8_t*>(p);
-    p += al256(nnames);
     a.pmask = reinterpret_cast<uint64_t*>(p);
 }
 

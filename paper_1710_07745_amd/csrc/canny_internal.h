@@ -85,9 +85,9 @@ struct HystArgs {
     int H, W;
     uint8_t* edges;
     int64_t epitch;
-    int32_t* blab;    // [ntiles * perim] global component name of each border pixel
-    int32_t* parent;  // [ntiles * 256] union-find forest over component names (tile * 256 + border index)
-    uint8_t* flag;    // [ntiles * 256] strong flags of the names (1 byte each)
+    int32_t* blab;    // [ntiles * perim] union-find key of each border pixel's component
+                      // (name tile * 256 + border index, plus 2^30 if weak; -1: none)
+    int32_t* parent;  // [ntiles * 256] union-find forest over keys, indexed by name
     uint64_t* pmask;  // [ntiles * 4] per wave of a tile: which thread segments hold pending codes
 };
 int hyst_tile_rows_default();
@@ -157,22 +157,22 @@ struct BatchImage {
     int64_t epitch;
     int H, W;
     int64_t cpitch;
-    int64_t cls_off, blab_off, parent_off, flag_off, pmask_off;  // bytes into the workspace
+    int64_t cls_off, blab_off, parent_off, pmask_off;  // bytes into the workspace
     int fwd_strips_x, fwd_base;  // forward wave tasks before this image
     int tiles_x, tiles_y, tile_base;
-    int merge_base, slot_base;
+    int merge_base;
 };
 struct BatchDev {
     char* ws;
     const int32_t* tile_img;  // image index of every tile of the batch (tile_base order)
     int n;
     int low, high;
-    int total_fwd, total_tiles, total_merge, total_slots;
+    int total_fwd, total_tiles, total_merge;
 };
 hipError_t launch_u8_forward_batch(const BatchImage* imgs, const BatchDev* hdr, int rows_per_wave,
                                    int total_fwd, hipStream_t s);
 hipError_t launch_hyst_batch(const BatchImage* imgs, const BatchDev* hdr, int total_tiles,
-                             int total_merge, int total_slots, hipStream_t s);
+                             int total_merge, hipStream_t s);
 
 size_t mag_partials(int N, int H, int W, int radius);
 hipError_t launch_mag_forward(const float* I, const float* sigma, int N, int H, int W, int radius,
