@@ -155,7 +155,7 @@ def roofline_headline(canny, torch, bufs, H, W, steps):
             "valu_insts_per_launch": valu_insts,
             "valu_frac": None if valu_insts is None else
             round(valu_insts * 64 / walk_s / VALU_PEAK_LANE_OPS, 4),
-            # Step 4's four passes (local, merge, flags, resolve) together,
+            # Step 4's three passes (local, merge, resolve) together,
             # on their algorithmic 0.25 B/px of class map in + 1 B/px of
             # edges out; on this path the local pass reads the 4 B/px signed
             # strength map instead of a class map (measured traffic in

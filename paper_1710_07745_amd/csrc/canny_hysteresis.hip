@@ -660,7 +660,8 @@ __device__ __forceinline__ void local_tile(const HystArgs& a, const TileGeom& g,
 // and each XCD has its own L2.  (Persistent forms -- as many workgroups as
 // the chip holds, each taking tile after tile, from per-XCD atomic counters
 // or in a fixed order -- measured slower: 65.9 and 61.7 against 55 us for the
-// four integer passes at 4096^2; so did static pairs of tiles per workgroup
+// integer hysteresis at 4096^2, then in four passes; so did static pairs of
+// tiles per workgroup
 // with the second one's loads issued early, 44 -> 57 us for the float pass.)
 template <int T>
 __global__ void __launch_bounds__(kWGThreads) k_hyst_local(HystArgs a, int tiles_x, int vec16) {
