@@ -670,38 +670,67 @@ __global__ void __launch_bounds__(kWGThreads) k_hyst_local(HystArgs a, int tiles
     local_tile<T>(a, g, load_raw<T>(a, g), vec16, sm);
 }
 
+// Unions of border key gp with the keys q[0..2] of its three neighbours across
+// the tile edge (-1: none).  Two components that are both strong need no
+// union: every set that either one joins is strong anyway.  When the previous
+// pixel along the edge has the same key (cont), that pixel's own unions
+// already cover q[0] and q[1] (they are its q[1] and q[2]), so only q[2]
+// remains, and only if it differs from q[1]; by induction along the run,
+// every pixel's three neighbours end up joined.  Repeats among consecutive
+// neighbours are skipped as well.
+__device__ __forceinline__ void merge_unions(int* parent, int gp, bool cont, const int (&q)[3]) {
+    int prev = cont ? q[1] : -1;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        if (cont && d < 2) continue;
+        const int gq = q[d];
+        if (gq >= 0 && gq != prev && (gp | gq) >= kWeakKey) g_union(parent, gp, gq);
+        prev = gq;
+    }
+}
+
 // Pass 2 for border pixel k of a tile (k < T: right edge row k; else bottom
-// edge column k - T).  Two components that are both strong need no union:
-// every set that either one joins is strong anyway.
+// edge column k - T).  All neighbour keys are loaded before the first union.
 template <int T>
 __device__ __forceinline__ void merge_one(const HystArgs& a, int tile, int k, int tiles_x, int tiles_y) {
     using TL = Tile<T>;
     const TileGeom g = tile_geom<T>(tile, tiles_x, a.H, a.W);
     const int base = tile * TL::kPerim;
+    int q[3];
     if (k < T) {  // right tile edge: pixel (k, tw-1) against column X0+64
         if (k >= g.th || g.tx + 1 >= tiles_x) return;
-        const int gp = a.blab[base + 2 * kHystCols + T + k];
+        const int* slots = a.blab + base + 2 * kHystCols + T;  // right column, row r at r
+        const int gp = slots[k];
+        const int gprev = k > 0 ? slots[k - 1] : -1;
         if (gp < 0) return;
         const int qx_tile = g.tx + 1;
-        for (int dy = -1; dy <= 1; ++dy) {
-            const int qy = g.Y0 + k + dy;
-            if (qy < 0 || qy >= a.H) continue;
-            const int qty = qy / T, qr = qy - qty * T;
-            const int gq = a.blab[(qty * tiles_x + qx_tile) * TL::kPerim + 2 * kHystCols + qr];
-            if (gq >= 0 && (gp | gq) >= kWeakKey) g_union(a.parent, gp, gq);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const int qy = g.Y0 + k + d - 1;
+            q[d] = -1;
+            if (qy >= 0 && qy < a.H) {
+                const int qty = qy / T, qr = qy - qty * T;
+                q[d] = a.blab[(qty * tiles_x + qx_tile) * TL::kPerim + 2 * kHystCols + qr];
+            }
         }
+        merge_unions(a.parent, gp, gprev == gp, q);
     } else {  // bottom tile edge: pixel (th-1, c) against row Y0+T
         const int c = k - T;
         if (c >= g.tw || g.ty + 1 >= tiles_y) return;
-        const int gp = a.blab[base + kHystCols + c];
+        const int* slots = a.blab + base + kHystCols;  // bottom row, column c at c
+        const int gp = slots[c];
+        const int gprev = c > 0 ? slots[c - 1] : -1;
         if (gp < 0) return;
-        for (int dx = -1; dx <= 1; ++dx) {
-            const int qx = g.X0 + c + dx;
-            if (qx < 0 || qx >= a.W) continue;
-            const int qtx = qx / kHystCols, qc = qx - qtx * kHystCols;
-            const int gq = a.blab[((g.ty + 1) * tiles_x + qtx) * TL::kPerim + qc];
-            if (gq >= 0 && (gp | gq) >= kWeakKey) g_union(a.parent, gp, gq);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const int qx = g.X0 + c + d - 1;
+            q[d] = -1;
+            if (qx >= 0 && qx < a.W) {
+                const int qtx = qx / kHystCols, qc = qx - qtx * kHystCols;
+                q[d] = a.blab[((g.ty + 1) * tiles_x + qtx) * TL::kPerim + qc];
+            }
         }
+        merge_unions(a.parent, gp, gprev == gp, q);
     }
 }
 
