@@ -325,10 +325,11 @@ __device__ __forceinline__ int ctz64(uint64_t v) { return __ffsll((long long)v) 
 // used), every root's entry carries its component's largest border index
 // and `strong` its strong bit.  cm and smk hold the 64-bit candidate and
 // strong masks of every tile row.
-//   phase 1: codes, row masks, L[i] = i for every pixel of the segment
+//   phase 1: codes, row masks
 //   phase 2: each run start with a run of the row above among its
 //            8-neighbours points at one of them (the one holding the lowest
-//            such column): a plain store, one writer per entry.  The runs
+//            such column), any other run start at itself: a plain store, one
+//            writer per entry (entries of other pixels are never read).  The runs
 //            now form trees that follow the image upwards, as deep as the
 //            tile is tall.
 //   phase 3: pointer jumping flattens the trees (each linked run start
@@ -359,12 +360,6 @@ __device__ __forceinline__ TileLabel<T> tile_label(uint32_t codes, const TileGeo
     st.strong = compress2((codes >> 1) & ~codes);  // code 2
     reinterpret_cast<uint16_t*>(cm)[r * 4 + seg] = (uint16_t)st.cand;
     reinterpret_cast<uint16_t*>(smk)[r * 4 + seg] = (uint16_t)st.strong;
-    {
-        int4* l4 = reinterpret_cast<int4*>(L + me + cb);
-        const int i0 = me + cb;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) l4[q] = make_int4(i0 + 4 * q, i0 + 4 * q + 1, i0 + 4 * q + 2, i0 + 4 * q + 3);
-    }
     __syncthreads();
     st.m = cm[r];
     st.S = st.m & ~(st.m << 1);
@@ -375,17 +370,22 @@ __device__ __forceinline__ TileLabel<T> tile_label(uint32_t codes, const TileGeo
     if (r > 0) {
         A = cm[r - 1];
         SA = A & ~(A << 1);
-        for (uint32_t b = starts; b; b &= b - 1) {
-            const int k = __ffs(b) - 1;
-            const uint64_t win = adj_window(st.m, cb + k);
-            const uint64_t ov = A & win;
-            if (ov) {
-                const int lo = ctz64(ov);
-                L[me + cb + k] = up + run_start(SA, lo);
-                linked |= 1u << k;
-                if (SA & win & ~((2ull << lo) - 1ull)) more |= 1u << k;
-            }
+    }
+    // only run starts' entries are ever read (every pointer, union and
+    // lookup goes through a run start), so each run start writes its own
+    // entry here: the run it points at, or itself
+    for (uint32_t b = starts; b; b &= b - 1) {
+        const int k = __ffs(b) - 1;
+        const uint64_t win = adj_window(st.m, cb + k);
+        const uint64_t ov = A & win;
+        int target = me + cb + k;
+        if (ov) {
+            const int lo = ctz64(ov);
+            target = up + run_start(SA, lo);
+            linked |= 1u << k;
+            if (SA & win & ~((2ull << lo) - 1ull)) more |= 1u << k;
         }
+        L[me + cb + k] = target;
     }
     __syncthreads();
     volatile lds_i32* V = lds_volatile(L);

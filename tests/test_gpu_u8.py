@@ -175,6 +175,68 @@ def test_hysteresis_long_chain(canny):
     assert np.array_equal(e, oe)
 
 
+def _line_classes(N, kind, seed_at):
+    """A one-pixel weak line across the whole image (16 tiles of 64 pixels),
+    strong at one position of it (or nowhere)."""
+    cls = np.zeros((N, N), np.uint8)
+    t = np.arange(N)
+    if kind == "row":
+        ys, xs = np.full(N, 100), t
+    elif kind == "col":
+        ys, xs = t, np.full(N, 37)
+    elif kind == "diag":  # crosses every tile corner diagonally: (63, 63) -> (64, 64)
+        ys, xs = t, t
+    else:  # anti-diagonal: (63, 64) -> (64, 63) corners
+        ys, xs = t, N - 1 - t
+    cls[ys, xs] = 1
+    if seed_at is not None:
+        k = {"first": 0, "middle": N // 2, "last": N - 1}[seed_at]
+        cls[ys[k], xs[k]] = 2
+    return cls
+
+
+def _comb_classes(N):
+    cls = np.zeros((N, N), np.uint8)
+    for r, seed in ((100, "all"), (300, "end"), (500, None)):
+        cls[r, :] = 2 if seed == "all" else 1
+        if seed == "end":
+            cls[r, N - 1] = 2
+        # teeth of uneven length, down at x = 5 mod 7 and up at x = 1 mod 7,
+        # so teeth of different combs are never 8-neighbours
+        for x in range(5, N - 3, 7):
+            ln = 20 + (x * 37) % 90
+            cls[r + 1:r + 1 + ln, x] = 1
+            cls[r - ln:r, x + 3] = 1
+    return cls
+
+
+@pytest.mark.parametrize("kind", ["row", "col", "diag", "anti"])
+@pytest.mark.parametrize("seed_at", ["first", "middle", "last", None])
+def test_hysteresis_strong_anywhere_on_chain(canny, kind, seed_at):
+    """One weak component spread over 16 tiles: its edge pixels appear iff a
+    strong pixel lies anywhere on it, whichever tile holds that pixel (the
+    strong tile's component name may be larger or smaller than those of the
+    weak tiles it is joined to)."""
+    N = 1024
+    cls = _line_classes(N, kind, seed_at)
+    e = run_hyst(canny, cls)
+    oe = oracle.hysteresis(cls)[0]
+    assert np.array_equal(e, oe)
+    assert int((e == 255).sum()) == (0 if seed_at is None else int((cls > 0).sum()))
+
+
+def test_hysteresis_combs(canny):
+    """Weak teeth hanging off spines that cross tile borders: a strong spine,
+    a weak spine seeded only at its far end, and a weak spine with no seed;
+    teeth cross the horizontal tile borders and touch each other only
+    through the spine."""
+    cls = _comb_classes(768)
+    e = run_hyst(canny, cls)
+    oe = oracle.hysteresis(cls)[0]
+    assert np.array_equal(e, oe)
+    assert e[300, :].min() == 255 and e[500, :].max() == 0
+
+
 def _oracle_classes_chunked(img, low, high, rows=1024, threads=16):
     """The oracle's class map of a large image, in row bands with a 4-row
     overlap (the integer pipeline reaches 4 rows: blur 2, Sobel 1,
