@@ -227,34 +227,53 @@ __device__ __forceinline__ RawSeg load_raw(const HystArgs& a, const TileGeom& g)
     return raw;
 }
 
-// Class codes (2 bits per pixel, pixel k at bits 2k) of the thread's 16
-// pixels; on the float path from the signed strength map: kept (value > 0)
-// and > hi -> 2, kept and >= lo -> 1.  Pixels past the image edge are 0.
+// Candidate and strong masks of the thread's 16 pixels (bit k: pixel k).
+// From the class map: code >= 1 and code 2.  From the signed strength map:
+// kept (value > 0) and >= lo, kept and > hi.  There the floats' bit patterns
+// are compared as int32: non-negative floats order like their bits and every
+// negative float (a suppressed pixel, -0 included) lies below them, so
+// "e > 0 and e >= lo" is bits(e) >= max(bits(lo), 1) and "e > hi" is
+// bits(e) > max(bits(hi), 0) (which also reads a threshold of -0 as 0) --
+// two compares per pixel and no branches.  Pixels past the image edge are 0.
+struct SegMasks {
+    uint32_t cand, strong;
+};
+
 template <int T>
-__device__ __forceinline__ uint32_t raw_codes(const HystArgs& a, const TileGeom& g, const RawSeg& raw, float mx) {
+__device__ __forceinline__ SegMasks raw_masks(const HystArgs& a, const TileGeom& g, const RawSeg& raw, float mx) {
     using TL = Tile<T>;
     const int t = g.t;
     const int r = t / TL::kTPR;
     const int cb = (t % TL::kTPR) * TL::kPPT;
-    if (r >= g.th) return 0u;
-    uint32_t codes = raw.cls;
+    SegMasks m = {0u, 0u};
+    if (r >= g.th) return m;
     if (a.smag) {
         const float lo = a.relative ? a.low * mx : a.low;
         const float hi = a.relative ? a.high * mx : a.high;
-        codes = 0;
+        const int lob = max(__float_as_int(lo), 1);
+        const int hib = max(__float_as_int(hi), 0);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const float e[4] = {raw.q[q].x, raw.q[q].y, raw.q[q].z, raw.q[q].w};
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                const uint32_t c = e[k] > 0.0f ? (e[k] > hi ? 2u : (e[k] >= lo ? 1u : 0u)) : 0u;
-                codes |= (q < raw.nq ? c : 0u) << (2 * (4 * q + k));
+                const int b = __float_as_int(e[k]);
+                m.cand |= (b >= lob ? 1u : 0u) << (4 * q + k);
+                m.strong |= (b > hib ? 1u : 0u) << (4 * q + k);
             }
         }
+        const uint32_t qm = raw.nq >= 4 ? 0xFFFFu : (1u << (4 * raw.nq)) - 1u;  // whole quads read
+        m.cand &= qm;
+        m.strong &= qm;
+    } else {
+        m.cand = compress2(raw.cls | (raw.cls >> 1));
+        m.strong = compress2((raw.cls >> 1) & ~raw.cls);  // code 2
     }
     const int valid = min(max(a.W - (g.X0 + cb), 0), TL::kPPT);
-    if (valid < 16) codes &= (valid == 0) ? 0u : (0xFFFFFFFFu >> (32 - 2 * valid));
-    return codes;
+    const uint32_t vm = valid >= 16 ? 0xFFFFu : (1u << valid) - 1u;
+    m.cand &= vm;
+    m.strong &= vm;
+    return m;
 }
 
 // Inclusive prefix sum over the 64 lanes of a wave: DPP row shifts within
@@ -319,13 +338,14 @@ __device__ __forceinline__ uint64_t adj_window(uint64_t m, int c0) {
 
 __device__ __forceinline__ int ctz64(uint64_t v) { return __ffsll((long long)v) - 1; }
 
-// Load this thread's class codes and label the tile's candidates in LDS.
+// Label the tile's candidates in LDS from this thread's candidate and strong
+// masks.
 // Afterwards L[r*64 + s] holds the root (smallest index) of the component
 // of the run that starts at column s of row r (only run starts' entries are
 // used), every root's entry carries its component's largest border index
 // and `strong` its strong bit.  cm and smk hold the 64-bit candidate and
 // strong masks of every tile row.
-//   phase 1: codes, row masks
+//   phase 1: row masks
 //   phase 2: each run start with a run of the row above among its
 //            8-neighbours points at one of them (the one holding the lowest
 //            such column), any other run start at itself: a plain store, one
@@ -344,7 +364,7 @@ __device__ __forceinline__ int ctz64(uint64_t v) { return __ffsll((long long)v) 
 // (wave_spread): a segment holds 0 to 8 of them, so per lane the counts are
 // uneven while a wave's total is small.
 template <int T>
-__device__ __forceinline__ TileLabel<T> tile_label(uint32_t codes, const TileGeom& g, int* L,
+__device__ __forceinline__ TileLabel<T> tile_label(SegMasks masks, const TileGeom& g, int* L,
                                                    uint64_t* cm, uint64_t* smk, uint32_t* strong,
                                                    uint32_t* list) {
     using TL = Tile<T>;
@@ -356,8 +376,8 @@ __device__ __forceinline__ TileLabel<T> tile_label(uint32_t codes, const TileGeo
     const int me = r * kHystCols;
     const int up = me - kHystCols;
     TileLabel<T> st;
-    st.cand = compress2(codes | (codes >> 1));
-    st.strong = compress2((codes >> 1) & ~codes);  // code 2
+    st.cand = masks.cand;
+    st.strong = masks.strong;
     reinterpret_cast<uint16_t*>(cm)[r * 4 + seg] = (uint16_t)st.cand;
     reinterpret_cast<uint16_t*>(smk)[r * 4 + seg] = (uint16_t)st.strong;
     __syncthreads();
@@ -592,7 +612,7 @@ __device__ __forceinline__ void local_tile(const HystArgs& a, const TileGeom& g,
         mx = __uint_as_float(mb);
         if (a.max_out && g.tile == 0 && t == 0) *a.max_out = mx;
     }
-    const TileLabel<T> st = tile_label<T>(raw_codes<T>(a, g, raw, mx), g, L, sm.cm, sm.smk, sm.strong,
+    const TileLabel<T> st = tile_label<T>(raw_masks<T>(a, g, raw, mx), g, L, sm.cm, sm.smk, sm.strong,
                                           sm.list + (t / kWave) * kWave);
     const int r = t / TL::kTPR;
     const int cb = (t % TL::kTPR) * TL::kPPT;
