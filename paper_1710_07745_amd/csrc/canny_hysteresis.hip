@@ -635,11 +635,16 @@ __device__ __forceinline__ void local_tile(const HystArgs& a, const TileGeom& g,
             const bool strong = (sm.strong[root >> 5] >> (root & 31)) & 1u;
             const bool pend = br != 0 && !strong;
             pending |= pend;
-            const uint32_t v = (pend ? br : (strong ? 255u : 0u)) * 0x01010101u;
+            // Byte permutes instead of 32-bit integer multiplies (those issue
+            // at a quarter of the VALU rate): selector 0 repeats byte 0 of
+            // the second operand, selectors 0x0C / 0x0D give 0x00 / 0xFF.
+            const uint32_t v = __builtin_amdgcn_perm(0u, pend ? br : (strong ? 255u : 0u), 0u);
             const uint32_t span = ((2u << k1) - 1u) & ~((1u << k0) - 1u);
 #pragma unroll
-            for (int q = 0; q < 4; ++q)  // bit j of a nibble -> byte j (0x00 / 0xFF)
-                w[q] |= ((((span >> (4 * q)) & 15u) * 0x00204081u) & 0x01010101u) * 0xFFu & v;
+            for (int q = 0; q < 4; ++q) {  // bit j of a nibble -> byte j (0x00 / 0xFF)
+                const uint32_t b = (((span >> (4 * q)) & 15u) * 0x00204081u) & 0x01010101u;  // 24-bit multiply
+                w[q] |= __builtin_amdgcn_perm(0u, 0u, b | 0x0C0C0C0Cu) & v;
+            }
         }
         Seg16 out;
         out.lo = w[0] | (uint64_t)w[1] << 32;
