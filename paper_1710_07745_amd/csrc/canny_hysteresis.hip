@@ -845,7 +845,6 @@ __global__ void __launch_bounds__(kWGThreads) k_hyst_resolve(HystArgs a, int til
 
 template <int T>
 hipError_t launch_t(const HystArgs& a, hipStream_t s) {
-    using TL = Tile<T>;
     const int tiles_x = ceil_div(a.W, kHystCols);
     const int tiles_y = ceil_div(a.H, T);
     const int ntiles = tiles_x * tiles_y;
