@@ -933,7 +933,7 @@ static size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 // blab: int32 per border slot; parent: int32 per component name (256 per
 // tile; only the names of this call's border components are written and
-// read); pmask: one 64-bit word per wave of a tile.  About 0.55 B per pixel.
+// read); pmask: one 64-bit word per wave of a tile.  About 0.51 B per pixel.
 size_t hyst_workspace_bytes(int H, int W, int tile_rows) {
     const size_t ntiles = (size_t)ceil_div(W, kHystCols) * ceil_div(H, tile_rows);
     const size_t nnames = ntiles * (size_t)kNamesPerTile;
