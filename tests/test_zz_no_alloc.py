@@ -51,3 +51,17 @@ def test_noalloc_rejects_too_large(canny):
     with pytest.raises(canny.CannyError) as ex:
         canny.canny_u8_noalloc(dev, 40, 100, edges=e)
     assert ex.value.status == canny._lib.CANNY_ERR_TOO_LARGE
+
+
+def test_noalloc_at_the_scratch_limit(canny):
+    """The largest square (a multiple of 64) whose workspace fits the scratch
+    runs and matches canny_u8; the next one up is rejected."""
+    lim = canny._lib.CANNY_NOALLOC_SCRATCH_BYTES
+    S = 64
+    while canny.u8_workspace_bytes(S + 64, S + 64) <= lim:
+        S += 64
+    one_call(canny, S, S, seed=63)
+    big = torch.zeros((S + 64, S + 64), dtype=torch.uint8, device="cuda")
+    with pytest.raises(canny.CannyError) as ex:
+        canny.canny_u8_noalloc(big, 40, 100, edges=torch.empty_like(big))
+    assert ex.value.status == canny._lib.CANNY_ERR_TOO_LARGE
