@@ -53,3 +53,36 @@ def test_one_past_the_limit_is_rejected(canny):
     y = torch.zeros((2, MAXD + 1), dtype=torch.float32, device="cuda")
     with pytest.raises(canny.CannyError):
         canny.canny_f32(y)
+
+
+def test_hysteresis_largest_names(canny):
+    """Step 4 at the largest pixel count the boundary accepts (46272^2:
+    522,729 tiles, so component names reach 1.34e8, just under 2^27): weak
+    lines across the whole image whose one strong pixel lies in the last tile
+    column, the last tile row or the bottom-right tile (the largest names),
+    and one with no strong pixel.  The class map is built on the GPU and the
+    exact edge map is known: every pixel of a seeded line is an edge, nothing
+    else is."""
+    H = W = 46272
+    assert (H // 64) * (W // 64) * 4096 < (1 << 31)
+    print(f"[largest names] {H}x{W}", flush=True)
+    P = canny.class_pitch(W)
+    cm = torch.zeros((H, P), dtype=torch.uint8, device="cuda")
+    want = torch.zeros((H, W), dtype=torch.uint8, device="cuda")
+    nb = W // 4
+    cm[100, :nb] = 0x55               # weak row, seeded at its right end
+    cm[100, nb - 1] = 0x95            # pixel W - 1: code 2
+    want[100, :] = 255
+    cm[300, :nb] = 0x55               # weak row, no strong pixel
+    ys = torch.arange(1000, H, device="cuda")
+    cm[ys, 37 // 4] = 1 << (2 * (37 % 4))  # weak column x = 37 from y = 1000, seeded at the bottom
+    cm[H - 1, 37 // 4] = 2 << (2 * (37 % 4))
+    want[1000:, 37] = 255
+    xs = ys                           # weak diagonal (y, y) from y = 1000, seeded at its end
+    cm[ys, xs // 4] = (1 << (2 * (xs % 4))).to(torch.uint8)
+    cm[H - 1, (W - 1) // 4] = 2 << (2 * ((W - 1) % 4))
+    want[ys, xs] = 255
+    e = canny.hysteresis(cm, H, W)
+    torch.cuda.synchronize()
+    assert int(e[300].max()) == 0
+    assert torch.equal(e, want)
