@@ -1,6 +1,9 @@
-"""The largest sizes the boundary accepts, per axis (H, W <= 2^20; the C ABI
+"""The largest sizes the boundary accepts.  Per axis (H, W <= 2^20; the C ABI
 rejects more): parity with the oracle on a 3 x 2^20 and a 2^20 x 3 image for
-the integer, float and four-sector paths, and rejection one past the limit."""
+the integer, float and four-sector paths, and rejection one past the limit.
+In pixel count (46272^2, the most 64 x 64 tiles whose pixel count stays
+below 2^31): hysteresis with a known answer at the largest component names,
+and the integer and float operators against the oracle on sampled windows."""
 import numpy as np
 import pytest
 import torch
@@ -86,3 +89,51 @@ def test_hysteresis_largest_names(canny):
     torch.cuda.synchronize()
     assert int(e[300].max()) == 0
     assert torch.equal(e, want)
+
+
+def _largest_pattern(H, W, dtype):
+    """A checkerboard of 37 x 53 rectangles (levels 60 and 160) built on the
+    GPU without wide temporaries."""
+    xr = ((torch.arange(W, device="cuda") // 37) % 2).to(torch.uint8)
+    yc = ((torch.arange(H, device="cuda") // 53) % 2).to(torch.uint8)
+    img = (xr[None, :] ^ yc[:, None]).mul_(100).add_(60)
+    return img if dtype == torch.uint8 else img.to(dtype)
+
+
+@pytest.mark.parametrize("path", ["u8", "f32"])
+def test_operator_largest_pixel_count(canny, path):
+    """The whole operator at the largest pixel count the boundary accepts
+    (46272^2).  Classes on sampled 64 x 64 windows (the corners and seeded
+    random ones) equal the oracle's on crops with a halo wider than the
+    operator's reach; the edge map equals Step 4 run by the standalone
+    hysteresis entry point on the returned class map (the float path with
+    absolute thresholds, so that a crop sees the thresholds of the image)."""
+    H = W = 46272
+    print(f"[largest {path}] {H}x{W}", flush=True)
+    if path == "u8":
+        img = _largest_pattern(H, W, torch.uint8)
+        e, cls = canny.canny_u8(img, 40, 100, return_classes=True)
+        halo = 6
+    else:
+        img = _largest_pattern(H, W, torch.float32)
+        e, cls = canny.canny_f32(img, 1.4, 3, 20.0, 60.0, False, return_classes=True)
+        halo = 8
+    torch.cuda.synchronize()
+    assert torch.equal(e, canny.hysteresis(cls, H, W))
+    rng = np.random.default_rng(5)
+    wins = [(0, 0), (H - 64, W - 64), (0, W - 64), (H - 64, 0)]
+    wins += [(int(rng.integers(0, H - 64)), int(rng.integers(0, (W - 64) // 4)) * 4) for _ in range(8)]
+    for y0, x0 in wins:
+        a, b = max(0, y0 - halo), min(H, y0 + 64 + halo)
+        c, d = max(0, x0 - halo), min(W, x0 + 64 + halo)
+        crop = img[a:b, c:d].cpu().numpy()
+        if path == "u8":
+            oc = oracle.classify_u8(crop, 40, 100)[0]
+            amb = np.zeros_like(oc)
+        else:
+            oc, _, amb, _ = oracle.classify_f32(crop, 1.4, 3, 20.0, 60.0, False)
+        oc = oc[y0 - a:y0 - a + 64, x0 - c:x0 - c + 64]
+        amb = amb[y0 - a:y0 - a + 64, x0 - c:x0 - c + 64]
+        gc = unpack_classes(cls[y0:y0 + 64, x0 // 4:x0 // 4 + 16].cpu().numpy(), 64, 64)
+        bad = (gc != oc) & ((amb & 3) == 0)
+        assert not bad.any(), f"window ({y0}, {x0}): {int(bad.sum())} class mismatches"
