@@ -91,11 +91,11 @@ def test_hysteresis_largest_names(canny):
     assert torch.equal(e, want)
 
 
-def _largest_pattern(H, W, dtype):
-    """A checkerboard of 37 x 53 rectangles (levels 60 and 160) built on the
+def _largest_pattern(H, W, dtype, px=37, py=53):
+    """A checkerboard of px x py rectangles (levels 60 and 160) built on the
     GPU without wide temporaries."""
-    xr = ((torch.arange(W, device="cuda") // 37) % 2).to(torch.uint8)
-    yc = ((torch.arange(H, device="cuda") // 53) % 2).to(torch.uint8)
+    xr = ((torch.arange(W, device="cuda") // px) % 2).to(torch.uint8)
+    yc = ((torch.arange(H, device="cuda") // py) % 2).to(torch.uint8)
     img = (xr[None, :] ^ yc[:, None]).mul_(100).add_(60)
     return img if dtype == torch.uint8 else img.to(dtype)
 
@@ -150,3 +150,20 @@ def test_operator_largest_pixel_count(canny, path):
         assert torch.equal(e_rel, e_cls)
         omx = oracle.classify_f32(img[20000:20400, 20000:20400].cpu().numpy())[3]
         assert abs(float(mx) - omx) <= 1e-5 * omx, (float(mx), omx)
+
+
+def test_batch_largest_images(canny):
+    """One batch plan over two images at (and near) the largest accepted size
+    and a small one: every image's edges equal canny_u8 on that image alone
+    (per-image tile, merge and name offsets at their largest)."""
+    shapes = [(46272, 46272), (1000, 1500), (46208, 46080)]
+    print(f"[largest batch] {shapes}", flush=True)
+    imgs = [_largest_pattern(h, w, torch.uint8, 37 + 4 * i, 53 - 6 * i) for i, (h, w) in enumerate(shapes)]
+    outs = [torch.empty((h, w), dtype=torch.uint8, device="cuda") for h, w in shapes]
+    plan = canny.BatchPlan(shapes, 40, 100, autotune=False)
+    ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device="cuda")
+    plan.run(imgs, outs, ws)
+    torch.cuda.synchronize()
+    for x, o in zip(imgs, outs):
+        assert torch.equal(o, canny.canny_u8(x, 40, 100))
+    plan.close()
