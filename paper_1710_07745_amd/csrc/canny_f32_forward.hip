@@ -289,9 +289,11 @@ __device__ __forceinline__ uint32_t f32_walk(const F32FwdArgs& a, int X0, int Y0
                     const float bdg = same ? ul : (domx ? dl : ur);
                     // with t = mn / mxv the interpolated neighbours are fp + t (fd - fp)
                     // and bp + t (bdg - bp); both sides are scaled by mxv > 0 instead
-                    // of dividing (mxv = 0 implies mc = 0, which is never kept)
-                    const float ahead = fmaf(mn, fd - fp, fp * mxv);
-                    const float behind = fmaf(mn, bdg - bp, bp * mxv);
+                    // of dividing (mxv = 0 implies mc = 0, which is never kept), as
+                    // fd mn + fp (mxv - mn) with the difference shared by both sides
+                    const float rest = mxv - mn;
+                    const float ahead = fmaf(fd, mn, fp * rest);
+                    const float behind = fmaf(bdg, mn, bp * rest);
                     const float ms = mc * mxv;
                     bool keep = mc > 0.0f && ms > behind && ms >= ahead;
                     if (SECTOR) {
